@@ -1,0 +1,178 @@
+/*
+ * pt_tebd.h -- C ABI of the MI355X PT-TEBD library (libpt_tebd.so).
+ *
+ * PT-TEBD (Fux, Kilda, Lovett, Keeling, arXiv 2201.05529) propagates the
+ * vectorised density matrix of a chain of open quantum systems as an
+ * "augmented" MPS whose site tensors carry one extra leg per bath: the bond
+ * of that bath's process-tensor MPO (PT-MPO).  One time step absorbs the
+ * PT-MPO tensor of every bath site and applies two-site Liouville-space
+ * propagators on the chain bonds (Sec. II.A; Appendix A).
+ *
+ * Problem statement (Appendix A, eq. total-hamiltonian): H = sum_n (H^S_n +
+ * H^E_n) + sum_n K_{n,n+1}, each environment H^E_n coupled to one site only,
+ * optional on-site GKSL terms (Appendix A.1).  The environments enter only
+ * through precomputed PT-MPOs (Appendix A.1, Fig. tensor-network-
+ * construction (b)); pt_mpo_build_ohmic() builds one for a Gaussian bath.
+ *
+ * Conventions shared by every call:
+ *  - complex numbers are interleaved (re, im) doubles; arrays are row-major;
+ *    sites are 0-based;
+ *  - Liouville index of one site: s = i*d + j for rho_ij (row-major vec);
+ *  - two-site operators K_{n,n+1} are given in the natural two-site order,
+ *    row (i_n i_{n+1}), column (j_n j_{n+1});
+ *  - the library copies every input it is given; the caller keeps ownership
+ *    of all its pointers and of the device workspace, which must outlive
+ *    the handle;
+ *  - no call throws; every call returns a status.  Errors found on the
+ *    device (non-finite numbers, a zero norm) are sticky per handle and are
+ *    reported by the next call that synchronises (observe, correlate,
+ *    bond_dims, snapshot); pt_tebd_last_error() gives a message.
+ *  - one host thread per handle at a time.  Work is enqueued on the HIP
+ *    stream given at creation; calls that return host data synchronise it.
+ */
+#ifndef PT_TEBD_H
+#define PT_TEBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pt_tebd* pt_tebd_t;
+
+typedef enum {
+  PT_TEBD_OK = 0,
+  PT_TEBD_EINVAL = -1,   /* invalid argument or configuration              */
+  PT_TEBD_ENOMEM = -2,   /* workspace too small                              */
+  PT_TEBD_EDEVICE = -3,  /* a HIP runtime call failed                        */
+  PT_TEBD_ENUMERIC = -4, /* non-finite value or zero norm met on the device  */
+  PT_TEBD_ENOCONV = -5,  /* an iterative eigensolver stage did not converge  */
+  PT_TEBD_ERANGE = -6    /* stepped past the end of a PT-MPO                 */
+} pt_tebd_status;
+
+typedef enum {
+  PT_TEBD_FP64 = 0,       /* every contraction in double precision            */
+  PT_TEBD_FP32_MIXED = 1  /* contractions in single precision on the matrix
+                             cores; Gram matrices, eigensolvers, singular
+                             values, bond vectors and scale in double        */
+} pt_tebd_precision;
+
+/* One bath: a PT-MPO attached to one site (Appendix A.1).  Tensor k
+ * (k = 1..n_steps) is P_k[e][e'][s_out][s_in] with e of dimension
+ * bond_dims[k-1] and e' of dimension bond_dims[k]; with diagonal = 1 (the
+ * coupling operator is diagonal in the computational basis) it is
+ * P_k[e][e'][s].  bond_dims[0] must be 1 (uncorrelated initial state).
+ * caps[k] (k = 0..n_steps) is the cap vector of step k (Appendix A.3) of
+ * length bond_dims[k]; caps = NULL makes the library compute them by the
+ * backward recursion (trace the output, feed the maximally mixed input). */
+typedef struct {
+  int32_t site;
+  int32_t n_steps;
+  const int32_t* bond_dims;      /* [n_steps + 1]                      */
+  int32_t diagonal;
+  const double* const* tensors;  /* [n_steps] pointers, complex        */
+  const double* const* caps;     /* [n_steps + 1] pointers or NULL     */
+} pt_tebd_bath;
+
+typedef struct {
+  int32_t n_sites;               /* N >= 1                                    */
+  int32_t d;                     /* local Hilbert dimension; must be 2        */
+  double dt;                     /* full time step, > 0                       */
+  const double* h_site;          /* [N][d][d] complex, Hermitian: H^S_n       */
+  const double* h_bond;          /* [N-1][d*d][d*d] complex, Hermitian: K     */
+  int32_t n_lindblad;            /* GKSL operators per site (may be 0)        */
+  const double* lindblad;        /* [N][n_lindblad][d][d] complex or NULL     */
+  const double* rho0;            /* [N][d][d] complex: product initial state  */
+  int32_t n_baths;               /* at most one bath per site                 */
+  const pt_tebd_bath* baths;
+  int32_t chi_max;               /* cap of the chain bond dimension           */
+  int32_t xi_max;                /* >= every PT-MPO bond dimension            */
+  double svd_rel_cutoff;         /* eps of the truncation rule (Appendix A.2) */
+  pt_tebd_precision precision;
+  uint64_t seed;                 /* seed of the randomised range finder       */
+} pt_tebd_config;
+
+/* Device workspace (bytes) a handle needs for cfg. */
+pt_tebd_status pt_tebd_workspace_size(const pt_tebd_config* cfg, size_t* bytes);
+
+/* Validate cfg, build the chain propagators (Appendix A.1: on-site terms
+ * absorbed into the bonds, second-order even/odd splitting, gates
+ * exp(L^{K'} dt/4) and the merged dt/2 gates), copy the PT-MPOs and the
+ * initial product state (Vidal form with dummy augmented legs, Appendix A.1)
+ * into the caller's device workspace, and return a handle.  hip_stream is a
+ * hipStream_t (NULL = default stream). */
+pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* dev_workspace, size_t bytes,
+                              void* hip_stream, pt_tebd_t* out);
+
+/* Enqueue n_steps time steps (eq. propagator-env): each is a chain half-step
+ * E(dt/4) O(dt/2) E(dt/4), the absorption of P_k on every bath site
+ * (Appendix A.2 (i)-(j)), and another chain half-step.  Each two-site gate
+ * uses the contraction and truncated-SVD sequence of Appendix A.2 (c)-(h).
+ * Asynchronous; returns PT_TEBD_ERANGE if the PT-MPOs are too short. */
+pt_tebd_status pt_tebd_step(pt_tebd_t h, int32_t n_steps);
+
+/* <O_i> = Tr[O_i rho] / Tr rho at the current step for n_ops single-site
+ * operators (ops: [n_ops][d][d] complex, sites: [n_ops]) via the caps of the
+ * current step (Appendix A.3, Fig. tensor-network-contraction (k)-(l)).
+ * out: [n_ops] complex.  trace_out (complex Tr rho, may be NULL).  Syncs. */
+pt_tebd_status pt_tebd_observe(pt_tebd_t h, int32_t n_ops, const int32_t* sites,
+                               const double* ops, double* out, double* trace_out);
+
+/* Two-time correlation (Appendix A.4, eq. two-time-corr-decomposed):
+ * out[j] = Tr[B X(t + j dt)] / Tr rho(t), j = 0..n_steps, where X(t) = A rho(t)
+ * (A acting on site_a from the left) is propagated from a device copy of the
+ * full augmented state.  The handle's own state is not changed.  Syncs. */
+pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a,
+                                 int32_t site_b, const double* op_b, int32_t n_steps,
+                                 double* out);
+
+/* Current chain bond dimensions chi[N-1] and augmented dims xi[N] (xi may be
+ * NULL).  Syncs. */
+pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi);
+
+/* Host copy of the whole augmented state (Gamma, lambda, log-scale, step).
+ * With buf = NULL only *bytes is set.  Syncs.  pt_tebd_restore loads it back
+ * into a handle created from the same configuration. */
+pt_tebd_status pt_tebd_snapshot(pt_tebd_t h, void* buf, size_t* bytes);
+pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes);
+
+int32_t pt_tebd_current_step(pt_tebd_t h);
+const char* pt_tebd_last_error(pt_tebd_t h);
+void pt_tebd_destroy(pt_tebd_t h);
+
+/* Enqueue n_steps time steps on n handles that share one HIP stream; the
+ * bond updates of each Trotter sublayer of all handles are batched into the
+ * same kernel launches. */
+pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps);
+
+/* Host helper (not on the hot path): PT-MPO of a Gaussian bosonic bath with
+ * J(w) = 2 alpha w exp(-w/wc) (cutoff_kind 0) or 2 alpha w exp(-w^2/wc^2)
+ * (cutoff_kind 1) at temperature T coupled through the d x d Hermitian
+ * operator coupling_op (complex), for time step dt, n_steps steps, memory
+ * cutoff mem_steps (Appendix B.1: Delta K_max) and truncation threshold eps
+ * (eps_TEMPO) with bond cap xi_max.  The influence functional is discretised
+ * for piecewise-constant system paths and compressed forward in time.
+ * out->tensors and out->bond_dims are allocated by the library; free them
+ * with pt_mpo_free.  out->caps is NULL. */
+pt_tebd_status pt_mpo_build_ohmic(double alpha, double wc, int32_t cutoff_kind, double temperature,
+                                  double dt, int32_t n_steps, int32_t mem_steps, double eps,
+                                  int32_t xi_max, const double* coupling_op, int32_t d,
+                                  pt_tebd_bath* out);
+void pt_mpo_free(pt_tebd_bath* bath);
+
+/* eta_Delta (Delta = 0..mem_steps) of the same discretisation, complex
+ * [mem_steps + 1]; exposed for testing. */
+pt_tebd_status pt_bath_eta(double alpha, double wc, int32_t cutoff_kind, double temperature,
+                           double dt, int32_t mem_steps, double* eta_out);
+
+/* The site-major two-site propagator of bond b (complex [d^4][d^4]) that
+ * pt_tebd_create built; exposed for testing.  Host-side, no sync. */
+pt_tebd_status pt_tebd_gate(pt_tebd_t h, int32_t bond, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_TEBD_H */

@@ -1,0 +1,31 @@
+/*
+ * pt_tebd_testing.h -- test-only entry points of libpt_tebd.so.
+ *
+ * They run one device kernel family of the PT-TEBD path on caller data so
+ * that it can be checked in isolation.  They allocate device memory with
+ * hipMalloc (not for use under graph capture) and synchronise.
+ */
+#ifndef PT_TEBD_TESTING_H
+#define PT_TEBD_TESTING_H
+
+#include "pt_tebd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Hermitian eigensolver of the truncated SVDs (Householder tridiagonal
+ * reduction, bisection, inverse iteration, back-transformation) on one n x n
+ * Hermitian matrix a (complex, row-major, n <= 1024).  rule: 0 every positive
+ * eigenvalue, 1 the eps rule on sqrt(eigenvalues), 2 the eps rule plus the
+ * cap, 3 numerical rank (lambda_k > eps * lambda_0).  Returns the eigenvalues
+ * in w[n] (descending), the selected eigenvectors in v (complex, row-major
+ * n x n, column k = vector k) and their number in *nvec. */
+pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
+                            double* w, double* v, int32_t* nvec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_TEBD_TESTING_H */

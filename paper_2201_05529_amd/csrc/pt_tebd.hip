@@ -1,0 +1,1029 @@
+// PT-TEBD engine and C ABI (include/pt_tebd.h).
+#include "pt_tebd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "chain_kernels.h"
+#include "host_math.h"
+
+using ptt::BathDev;
+using ptt::BondJob;
+using ptt::ChainDev;
+using ptt::cplx;
+using ptt::HeevJob;
+using ptt::ObsScratch;
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// ------------------------------------------------------------- bump alloc
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Sublayer {
+  std::vector<int> bonds;
+  BondJob* jobs = nullptr;       // device
+  HeevJob* heev_b = nullptr;     // device [2 n]
+  HeevJob* heev_oy = nullptr;    // device [n]
+  HeevJob* heev_oz = nullptr;    // device [n]
+  HeevJob* heev_rr = nullptr;    // device [n]
+  std::vector<BondJob> host_jobs;
+};
+
+struct Caps {
+  int n_sites, chi_cap, xi_cap, nb, dn, kc, nh, n_slots;
+  long long gam_cap;
+};
+
+}  // namespace
+
+struct pt_tebd {
+  // configuration
+  int n_sites = 0, d = 2;
+  double dt = 0.0;
+  int chi_max = 1, xi_max = 1;
+  double eps = 0.0;
+  pt_tebd_precision precision = PT_TEBD_FP64;
+  unsigned long long seed = 0;
+  int power_iters = 1;
+  int oversample = 64;
+  int pt_steps = 0;           // shortest PT-MPO length
+  Caps cap{};
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<std::vector<cplx>> gates_host;
+  // device
+  ChainDev* chains = nullptr;  // [2]: main, fork
+  ChainDev chain_host[2];
+  double2* gates = nullptr;
+  BathDev* baths = nullptr;
+  int n_baths = 0;
+  int* bath_of_site = nullptr;
+  std::vector<int> bath_of_site_host;
+  ObsScratch obs{};
+  int ops_cap = 0;
+  int* ops_sites = nullptr;
+  double2* ops_vec = nullptr;
+  double2* ops_out = nullptr;
+  double* ops_log = nullptr;
+  double2* site_op = nullptr;  // [16] super-operator for correlate
+  Sublayer sub_even, sub_odd;  // 1-based even bonds (0-based odd), 1-based odd bonds
+  int step = 0;
+  std::string err;
+};
+
+namespace {
+
+Caps compute_caps(const pt_tebd_config* cfg, int oversample) {
+  Caps c{};
+  c.n_sites = cfg->n_sites;
+  c.chi_cap = std::max(1, cfg->chi_max);
+  c.xi_cap = std::max(1, cfg->xi_max);
+  c.nb = 4 * c.chi_cap;
+  c.dn = 4 * c.nb;
+  c.kc = std::min(c.dn, c.chi_cap + oversample);
+  c.nh = std::max(c.nb, c.kc);
+  c.n_slots = cfg->n_sites / 2;  // max(#even, #odd) bonds = floor(N/2)
+  c.gam_cap = (long long)c.chi_cap * 4 * c.xi_cap * c.chi_cap;
+  return c;
+}
+
+struct DevPtrs {
+  // per chain (x2)
+  double2* gam[2];
+  int* parity[2];
+  int* chi[2];
+  int* xi[2];
+  double* lam[2];
+  double* log_scale[2];
+  int* status[2];
+  ChainDev* chains;
+  double2* gates;
+  BathDev* baths;
+  int* bath_of_site;
+  std::vector<double2*> bath_tens;
+  std::vector<long long*> bath_toff;
+  std::vector<int*> bath_dims;
+  std::vector<double2*> bath_caps;
+  std::vector<long long*> bath_coff;
+  ObsScratch obs;
+  int* ops_sites;
+  double2* ops_vec;
+  double2* ops_out;
+  double* ops_log;
+  double2* site_op;
+  std::vector<BondJob> slots;          // scratch per slot (bond fields unset)
+  std::vector<double2*> h_refl[2];
+  std::vector<double*> h_tri[2], h_work[2], h_z[2];
+  BondJob* jobs[2];
+  HeevJob *hb[2], *hoy[2], *hoz[2], *hrr[2];
+};
+
+// Walk the workspace layout once with a null base (sizes only) or with the
+// real base (pointers).
+size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long long>& bath_tens_len,
+              const std::vector<long long>& bath_caps_len, void* base, DevPtrs* out) {
+  Bump bp(base);
+  DevPtrs P;
+  const int N = c.n_sites;
+  for (int k = 0; k < 2; ++k) {
+    P.gam[k] = bp.take<double2>((size_t)N * 2 * c.gam_cap);
+    P.parity[k] = bp.take<int>(N);
+    P.chi[k] = bp.take<int>(N + 1);
+    P.xi[k] = bp.take<int>(N);
+    P.lam[k] = bp.take<double>((size_t)(N + 1) * c.chi_cap);
+    P.log_scale[k] = bp.take<double>(1);
+    P.status[k] = bp.take<int>(1);
+  }
+  P.chains = bp.take<ChainDev>(2);
+  P.gates = bp.take<double2>((size_t)std::max(N - 1, 1) * 256);
+  const int nbath = cfg->n_baths;
+  P.baths = bp.take<BathDev>(std::max(nbath, 1));
+  P.bath_of_site = bp.take<int>(N);
+  for (int i = 0; i < nbath; ++i) {
+    const int m = cfg->baths[i].n_steps;
+    P.bath_tens.push_back(bp.take<double2>(bath_tens_len[i]));
+    P.bath_toff.push_back(bp.take<long long>(m));
+    P.bath_dims.push_back(bp.take<int>(m + 1));
+    P.bath_caps.push_back(bp.take<double2>(bath_caps_len[i]));
+    P.bath_coff.push_back(bp.take<long long>(m + 1));
+  }
+  P.obs.hat = bp.take<double2>((size_t)N * c.chi_cap * 4 * c.chi_cap);
+  P.obs.lvec = bp.take<double2>((size_t)(N + 1) * c.chi_cap);
+  P.obs.rvec = bp.take<double2>((size_t)(N + 1) * c.chi_cap);
+  P.obs.llog = bp.take<double>(N + 1);
+  P.obs.rlog = bp.take<double>(N + 1);
+  const int ops_cap = 8 * N + 8;
+  P.ops_sites = bp.take<int>(ops_cap);
+  P.ops_vec = bp.take<double2>((size_t)ops_cap * 4);
+  P.ops_out = bp.take<double2>((size_t)ops_cap * 2);
+  P.ops_log = bp.take<double>(ops_cap);
+  P.site_op = bp.take<double2>(16);
+  const size_t rl = (size_t)c.chi_cap * c.xi_cap, nb = c.nb, dn = c.dn, kc = c.kc, nh = c.nh;
+  for (int s = 0; s < c.n_slots; ++s) {
+    BondJob J{};
+    J.dims = bp.take<int>(ptt::D_COUNT);
+    J.norms = bp.take<double>(4);
+    J.bl = bp.take<double2>(rl * nb);
+    J.br = bp.take<double2>(nb * rl);
+    J.gl = bp.take<double2>(nb * nb);
+    J.gr = bp.take<double2>(nb * nb);
+    J.vl = bp.take<double2>(nb * nb);
+    J.vr = bp.take<double2>(nb * nb);
+    J.wl = bp.take<double>(nh);
+    J.wr = bp.take<double>(nh);
+    J.x = bp.take<double2>(nb * nb);
+    J.y = bp.take<double2>(nb * nb);
+    J.p = bp.take<double2>(dn * dn);
+    J.d = bp.take<double2>(dn * dn);
+    J.wk = bp.take<double>(nh);
+    J.omega = bp.take<double2>(dn * kc);
+    J.ya = bp.take<double2>(dn * kc);
+    J.yb = bp.take<double2>(dn * kc);
+    J.za = bp.take<double2>(dn * kc);
+    J.zb = bp.take<double2>(dn * kc);
+    J.gk = bp.take<double2>(kc * kc);
+    J.vk = bp.take<double2>(kc * kc);
+    J.bm = bp.take<double2>(kc * dn);
+    J.ud = bp.take<double2>(dn * c.chi_cap);
+    J.vdh = bp.take<double2>((size_t)c.chi_cap * dn);
+    J.t1 = bp.take<double2>(4 * (size_t)c.chi_cap * nb);
+    J.tg = bp.take<double2>(4 * (size_t)c.chi_cap * rl);
+    P.slots.push_back(J);
+    for (int set = 0; set < 2; ++set) {
+      P.h_refl[set].push_back(bp.take<double2>(nh * nh));
+      P.h_tri[set].push_back(bp.take<double>(6 * nh));
+      P.h_work[set].push_back(bp.take<double>(8 * nh * nh));
+      P.h_z[set].push_back(bp.take<double>(nh * nh));
+    }
+  }
+  for (int par = 0; par < 2; ++par) {
+    const int n = std::max(c.n_slots, 1);
+    P.jobs[par] = bp.take<BondJob>(n);
+    P.hb[par] = bp.take<HeevJob>(2 * n);
+    P.hoy[par] = bp.take<HeevJob>(n);
+    P.hoz[par] = bp.take<HeevJob>(n);
+    P.hrr[par] = bp.take<HeevJob>(n);
+  }
+  if (out) *out = P;
+  return bp.off + 256;
+}
+
+bool check(hipError_t e, pt_tebd* h, const char* what) {
+  if (e == hipSuccess) return true;
+  if (h) h->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+pt_tebd_status validate(const pt_tebd_config* cfg, std::string& err) {
+  if (!cfg) { err = "null config"; return PT_TEBD_EINVAL; }
+  if (cfg->n_sites < 1) { err = "n_sites must be >= 1"; return PT_TEBD_EINVAL; }
+  if (cfg->d != 2) { err = "only d = 2 (spin-1/2) sites are supported"; return PT_TEBD_EINVAL; }
+  if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) { err = "dt must be positive"; return PT_TEBD_EINVAL; }
+  if (cfg->chi_max < 1 || cfg->chi_max > 256) { err = "chi_max must be in [1, 256]"; return PT_TEBD_EINVAL; }
+  if (cfg->xi_max < 1 || cfg->xi_max > 1024) { err = "xi_max must be in [1, 1024]"; return PT_TEBD_EINVAL; }
+  if (!(cfg->svd_rel_cutoff >= 0.0) || !(cfg->svd_rel_cutoff < 1.0)) { err = "svd_rel_cutoff must be in [0, 1)"; return PT_TEBD_EINVAL; }
+  if (!cfg->h_site || !cfg->rho0 || (cfg->n_sites > 1 && !cfg->h_bond)) { err = "missing h_site, h_bond or rho0"; return PT_TEBD_EINVAL; }
+  if (cfg->n_lindblad < 0 || (cfg->n_lindblad > 0 && !cfg->lindblad)) { err = "bad lindblad"; return PT_TEBD_EINVAL; }
+  if (cfg->precision != PT_TEBD_FP64 && cfg->precision != PT_TEBD_FP32_MIXED) { err = "bad precision"; return PT_TEBD_EINVAL; }
+  if (cfg->n_baths < 0 || cfg->n_baths > cfg->n_sites || (cfg->n_baths > 0 && !cfg->baths)) { err = "bad baths"; return PT_TEBD_EINVAL; }
+  const int N = cfg->n_sites;
+  auto herm = [](const double* m, int n) {
+    double scale = 0.0, dev = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double ar = m[2 * (i * n + j)], ai = m[2 * (i * n + j) + 1];
+        const double br = m[2 * (j * n + i)], bi = -m[2 * (j * n + i) + 1];
+        if (!std::isfinite(ar) || !std::isfinite(ai)) return false;
+        scale = std::max(scale, std::fabs(ar) + std::fabs(ai));
+        dev = std::max(dev, std::fabs(ar - br) + std::fabs(ai - bi));
+      }
+    return dev <= 1e-10 * std::max(scale, 1.0);
+  };
+  for (int n = 0; n < N; ++n)
+    if (!herm(cfg->h_site + 8 * n, 2)) { err = "h_site must be finite and Hermitian"; return PT_TEBD_EINVAL; }
+  for (int b = 0; b + 1 < N; ++b)
+    if (!herm(cfg->h_bond + 32 * b, 4)) { err = "h_bond must be finite and Hermitian"; return PT_TEBD_EINVAL; }
+  for (int i = 0; i < 8 * N; ++i)
+    if (!std::isfinite(cfg->rho0[i])) { err = "rho0 must be finite"; return PT_TEBD_EINVAL; }
+  std::vector<int> used(N, 0);
+  for (int i = 0; i < cfg->n_baths; ++i) {
+    const pt_tebd_bath& b = cfg->baths[i];
+    if (b.site < 0 || b.site >= N || used[b.site]) { err = "bath sites must be distinct and in range"; return PT_TEBD_EINVAL; }
+    used[b.site] = 1;
+    if (b.n_steps < 1 || !b.bond_dims || !b.tensors) { err = "bath needs n_steps >= 1, bond_dims and tensors"; return PT_TEBD_EINVAL; }
+    if (b.bond_dims[0] != 1) { err = "PT-MPO bond_dims[0] must be 1"; return PT_TEBD_EINVAL; }
+    for (int k = 0; k <= b.n_steps; ++k)
+      if (b.bond_dims[k] < 1 || b.bond_dims[k] > cfg->xi_max) { err = "PT-MPO bond dimension outside [1, xi_max]"; return PT_TEBD_EINVAL; }
+    const int per = b.diagonal ? 4 : 16;
+    for (int k = 0; k < b.n_steps; ++k) {
+      if (!b.tensors[k]) { err = "null PT-MPO tensor"; return PT_TEBD_EINVAL; }
+      const long long len = 2LL * b.bond_dims[k] * b.bond_dims[k + 1] * per;
+      for (long long q = 0; q < len; ++q)
+        if (!std::isfinite(b.tensors[k][q])) { err = "non-finite PT-MPO tensor entry"; return PT_TEBD_ENUMERIC; }
+    }
+  }
+  return PT_TEBD_OK;
+}
+
+std::vector<long long> tensor_lengths(const pt_tebd_config* cfg) {
+  std::vector<long long> out;
+  for (int i = 0; i < cfg->n_baths; ++i) {
+    const pt_tebd_bath& b = cfg->baths[i];
+    long long t = 0;
+    const int per = b.diagonal ? 4 : 16;
+    for (int k = 0; k < b.n_steps; ++k) t += (long long)b.bond_dims[k] * b.bond_dims[k + 1] * per;
+    out.push_back(std::max(t, 1LL));
+  }
+  return out;
+}
+
+std::vector<long long> cap_lengths(const pt_tebd_config* cfg) {
+  std::vector<long long> out;
+  for (int i = 0; i < cfg->n_baths; ++i) {
+    const pt_tebd_bath& b = cfg->baths[i];
+    long long t = 0;
+    for (int k = 0; k <= b.n_steps; ++k) t += b.bond_dims[k];
+    out.push_back(std::max(t, 1LL));
+  }
+  return out;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+// ----------------------------------------------------------------- launch
+void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int subs, int m_cap, int n_cap) {
+  dim3 grid((m_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (n_cap + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_items * subs);
+  ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs);
+}
+
+void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
+  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_THREADS, 0, st>>>(jobs);
+  dim3 grid((n_cap + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, n_jobs);
+  const size_t shm = (size_t)n_cap * ptt::HEEV_BT_COLS * sizeof(double2);
+  ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, shm, st>>>(jobs);
+}
+
+int elem_blocks(long long n) { return (int)std::min<long long>(std::max<long long>((n + kThreads - 1) / kThreads, 1), 1024); }
+
+void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
+  const int n = (int)S.bonds.size();
+  if (n == 0) return;
+  const Caps& c = h->cap;
+  hipStream_t st = h->stream;
+  const long long rl = (long long)c.chi_cap * c.xi_cap;
+  const BondJob* J = S.jobs;
+  const int eb = elem_blocks(2 * rl * c.nb);
+  ptt::k_pack<<<dim3(eb, n), kThreads, 0, st>>>(chains, J);
+  launch_gemm(st, J, n, ptt::GK_GRAM_B, 2, c.nb, c.nb);
+  launch_heev(st, S.heev_b, 2 * n, c.nh);
+  launch_gemm(st, J, n, ptt::GK_XY, 2, c.nb, c.nb);
+  ptt::k_form_xy<<<dim3(elem_blocks(2LL * c.nb * c.nb), n), kThreads, 0, st>>>(chains, J);
+  launch_gemm(st, J, n, ptt::GK_P, 1, c.dn, c.dn);
+  ptt::k_apply_gate<<<dim3(elem_blocks((long long)c.nb * c.nb), n), kThreads, 0, st>>>(J);
+  ptt::k_sketch_init<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J);
+  launch_gemm(st, J, n, ptt::GK_SKETCH, 1, c.dn, c.kc);
+  auto copy_dim = [&](int dst, int src) { ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, dst, src); };
+  auto orth_y = [&]() {
+    launch_gemm(st, J, n, ptt::GK_GRAM_YA, 1, c.kc, c.kc);
+    launch_heev(st, S.heev_oy, n, c.kc);
+    launch_gemm(st, J, n, ptt::GK_APPLY_YA, 1, c.dn, c.kc);
+    copy_dim(ptt::D_GS, ptt::D_KQ);
+    launch_gemm(st, J, n, ptt::GK_GRAM_YB, 1, c.kc, c.kc);
+    launch_heev(st, S.heev_oy, n, c.kc);
+    launch_gemm(st, J, n, ptt::GK_APPLY_YB, 1, c.dn, c.kc);
+  };
+  orth_y();
+  for (int it = 0; it < h->power_iters; ++it) {
+    launch_gemm(st, J, n, ptt::GK_DH_Q, 1, c.dn, c.kc);
+    copy_dim(ptt::D_GS, ptt::D_KQ);
+    launch_gemm(st, J, n, ptt::GK_GRAM_ZA, 1, c.kc, c.kc);
+    launch_heev(st, S.heev_oz, n, c.kc);
+    launch_gemm(st, J, n, ptt::GK_APPLY_ZA, 1, c.dn, c.kc);
+    copy_dim(ptt::D_GS, ptt::D_KZ);
+    launch_gemm(st, J, n, ptt::GK_GRAM_ZB, 1, c.kc, c.kc);
+    launch_heev(st, S.heev_oz, n, c.kc);
+    launch_gemm(st, J, n, ptt::GK_APPLY_ZB, 1, c.dn, c.kc);
+    launch_gemm(st, J, n, ptt::GK_D_Z, 1, c.dn, c.kc);
+    copy_dim(ptt::D_GS, ptt::D_KZ);
+    orth_y();
+  }
+  launch_gemm(st, J, n, ptt::GK_QH_D, 1, c.kc, c.dn);
+  ptt::k_rr_norms<<<n, kThreads, 0, st>>>(J);
+  copy_dim(ptt::D_GS, ptt::D_KQ);
+  launch_gemm(st, J, n, ptt::GK_GRAM_BM, 1, c.kc, c.kc);
+  launch_heev(st, S.heev_rr, n, c.kc);
+  launch_gemm(st, J, n, ptt::GK_UD, 1, c.dn, c.chi_cap);
+  launch_gemm(st, J, n, ptt::GK_VDH, 1, c.chi_cap, c.dn);
+  ptt::k_scale_factors<<<dim3(elem_blocks(2LL * c.dn * c.chi_cap), n), kThreads, 0, st>>>(J);
+  launch_gemm(st, J, n, ptt::GK_T1, 1, c.nb, 4 * c.chi_cap);
+  launch_gemm(st, J, n, ptt::GK_NEWL, 1, (int)rl, 4 * c.chi_cap);
+  ptt::k_store_gamma<<<dim3(elem_blocks(rl * 4 * c.chi_cap), n), kThreads, 0, st>>>(chains, J, 0);
+  launch_gemm(st, J, n, ptt::GK_T2, 1, 4 * c.chi_cap, c.nb);
+  launch_gemm(st, J, n, ptt::GK_NEWR, 1, 4 * c.chi_cap, (int)rl);
+  ptt::k_store_gamma<<<dim3(elem_blocks(rl * 4 * c.chi_cap), n), kThreads, 0, st>>>(chains, J, 1);
+  ptt::k_finalize<<<n, kThreads, 0, st>>>(chains, J);
+}
+
+void run_half_step(pt_tebd* h, const ChainDev* chains, ChainDev* host_view, double2* /*unused*/) {
+  (void)host_view;
+  if (h->n_sites == 1) {
+    ptt::k_apply_site_op<<<elem_blocks((long long)h->cap.chi_cap * h->cap.xi_cap * h->cap.chi_cap), kThreads, 0,
+                           h->stream>>>(chains, 0, h->gates);
+    return;
+  }
+  // E(dt/4) O(dt/2) E(dt/4) with 1-based bond parity: E = 0-based odd bonds
+  run_sublayer(h, h->sub_even, chains);
+  run_sublayer(h, h->sub_odd, chains);
+  run_sublayer(h, h->sub_even, chains);
+}
+
+pt_tebd_status device_status(pt_tebd* h, int which) {
+  int st = 0;
+  if (!check(hipMemcpyAsync(&st, h->chain_host[which].status, sizeof(int), hipMemcpyDeviceToHost, h->stream), h,
+             "status copy") ||
+      !check(hipStreamSynchronize(h->stream), h, "stream sync"))
+    return PT_TEBD_EDEVICE;
+  if (st & ptt::ST_RANGE) { h->err = "PT-MPO step or bond dimension mismatch on the device"; return PT_TEBD_ERANGE; }
+  if (st & (ptt::ST_NONFINITE | ptt::ST_ZERO)) { h->err = "non-finite value or zero norm during a bond update"; return PT_TEBD_ENUMERIC; }
+  if (st & ptt::ST_EIG) { h->err = "eigensolver produced a non-finite value"; return PT_TEBD_ENUMERIC; }
+  return PT_TEBD_OK;
+}
+
+void step_chain(pt_tebd* h, int which, int k) {
+  const ChainDev* chains = h->chains + which;
+  // the sublayer jobs index chain 0 of the array they are given
+  run_half_step(h, chains, nullptr, nullptr);
+  if (h->n_baths > 0) {
+    ptt::k_pt_absorb<<<dim3(elem_blocks((long long)h->cap.chi_cap * 4 * h->cap.xi_cap * h->cap.chi_cap), h->n_baths),
+                       kThreads, 0, h->stream>>>(chains, h->baths, k);
+    ptt::k_pt_commit<<<1, 64 * ((h->n_baths + 63) / 64), 0, h->stream>>>(chains, h->baths, h->n_baths, k);
+  }
+  run_half_step(h, chains, nullptr, nullptr);
+}
+
+// observe on chain `which` at PT step `k`: fills host num/den/log
+pt_tebd_status observe_raw(pt_tebd* h, int which, int k, int n_ops, const int* sites, const double* ovec_host,
+                           std::vector<std::complex<double>>& num, std::vector<std::complex<double>>& den,
+                           std::vector<double>& lg) {
+  const ChainDev* chains = h->chains + which;
+  const Caps& c = h->cap;
+  ptt::k_obs_hat<<<dim3(elem_blocks((long long)c.chi_cap * 4 * c.chi_cap), c.n_sites), kThreads, 0, h->stream>>>(
+      chains, h->baths, h->bath_of_site, k, h->obs);
+  ptt::k_obs_scan<<<1, kThreads, 0, h->stream>>>(chains, h->obs);
+  num.assign(n_ops, 0.0);
+  den.assign(n_ops, 0.0);
+  lg.assign(n_ops, 0.0);
+  for (int off = 0; off < n_ops; off += h->ops_cap) {
+    const int cnt = std::min(h->ops_cap, n_ops - off);
+    if (!check(hipMemcpyAsync(h->ops_sites, sites + off, cnt * sizeof(int), hipMemcpyHostToDevice, h->stream), h, "ops copy") ||
+        !check(hipMemcpyAsync(h->ops_vec, ovec_host + 8 * off, cnt * 4 * sizeof(double2), hipMemcpyHostToDevice, h->stream), h, "ops copy"))
+      return PT_TEBD_EDEVICE;
+    ptt::k_obs_ops<<<cnt, kThreads, 0, h->stream>>>(chains, h->obs, h->ops_sites, h->ops_vec, h->ops_out, h->ops_log);
+    std::vector<double2> out(2 * cnt);
+    std::vector<double> lgo(cnt);
+    if (!check(hipMemcpyAsync(out.data(), h->ops_out, 2 * cnt * sizeof(double2), hipMemcpyDeviceToHost, h->stream), h, "ops out") ||
+        !check(hipMemcpyAsync(lgo.data(), h->ops_log, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream), h, "ops out") ||
+        !check(hipStreamSynchronize(h->stream), h, "stream sync"))
+      return PT_TEBD_EDEVICE;
+    for (int i = 0; i < cnt; ++i) {
+      num[off + i] = {out[2 * i].x, out[2 * i].y};
+      den[off + i] = {out[2 * i + 1].x, out[2 * i + 1].y};
+      lg[off + i] = lgo[i];
+    }
+  }
+  return device_status(h, which);
+}
+
+// observable vector o with o . vec(rho) = Tr[op rho]: o[i*d+j] = op[j][i]
+void obs_vector(const double* op, double* o) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      o[2 * (i * 2 + j)] = op[2 * (j * 2 + i)];
+      o[2 * (i * 2 + j) + 1] = op[2 * (j * 2 + i) + 1];
+    }
+}
+
+void fill_heev(HeevJob& H, double2* a, int lda, int* n_ptr, double* w, double2* refl, double* tri, double* work,
+               double* z, int n_cap, int* nvec, int rule, double eps, int capv, const double* extra, double rank_tol,
+               double2* v, int ldv, int scale, int* status) {
+  H.a = a; H.lda = lda; H.n_ptr = n_ptr; H.w = w; H.refl = refl; H.tri = tri; H.work = work; H.z = z;
+  H.n_cap = n_cap; H.nvec_out = nvec; H.rule = rule; H.eps = eps; H.cap = capv; H.extra_tail = extra;
+  H.rank_tol = rank_tol; H.v = v; H.ldv = ldv; H.scale = scale; H.status = status;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+pt_tebd_status pt_tebd_workspace_size(const pt_tebd_config* cfg, size_t* bytes) {
+  std::string err;
+  if (!bytes) return PT_TEBD_EINVAL;
+  const pt_tebd_status s = validate(cfg, err);
+  if (s != PT_TEBD_OK) return s;
+  const Caps c = compute_caps(cfg, env_int("PT_TEBD_OVERSAMPLE", 64));
+  *bytes = layout(c, cfg, tensor_lengths(cfg), cap_lengths(cfg), nullptr, nullptr);
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes, void* stream, pt_tebd_t* out) {
+  if (!out) return PT_TEBD_EINVAL;
+  *out = nullptr;
+  std::string err;
+  pt_tebd_status s = validate(cfg, err);
+  if (s != PT_TEBD_OK) return s;
+  if (!ws) return PT_TEBD_EINVAL;
+  auto h = std::make_unique<pt_tebd>();
+  h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
+  h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
+  h->cap = compute_caps(cfg, h->oversample);
+  const Caps& c = h->cap;
+  const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
+  const size_t need = layout(c, cfg, tl, cl, nullptr, nullptr);
+  if (bytes < need) return PT_TEBD_ENOMEM;
+  DevPtrs P;
+  layout(c, cfg, tl, cl, ws, &P);
+  h->n_sites = cfg->n_sites;
+  h->d = cfg->d;
+  h->dt = cfg->dt;
+  h->chi_max = cfg->chi_max;
+  h->xi_max = cfg->xi_max;
+  h->eps = cfg->svd_rel_cutoff;
+  h->precision = cfg->precision;
+  h->seed = cfg->seed;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ws = ws;
+  h->ws_bytes = bytes;
+  const int N = cfg->n_sites;
+  hipStream_t st = h->stream;
+  pt_tebd* hp = h.get();
+
+  // chain propagators (host, double precision)
+  std::vector<cplx> hs(4 * N), hb(16 * std::max(N - 1, 0)), lind;
+  for (int i = 0; i < 4 * N; ++i) hs[i] = {cfg->h_site[2 * i], cfg->h_site[2 * i + 1]};
+  for (size_t i = 0; i < hb.size(); ++i) hb[i] = {cfg->h_bond[2 * i], cfg->h_bond[2 * i + 1]};
+  if (cfg->n_lindblad > 0) {
+    lind.resize((size_t)N * cfg->n_lindblad * 4);
+    for (size_t i = 0; i < lind.size(); ++i) lind[i] = {cfg->lindblad[2 * i], cfg->lindblad[2 * i + 1]};
+  }
+  h->gates_host = ptt::chain_gates(N, 2, cfg->dt, hs.data(), hb.data(), cfg->n_lindblad, lind.data());
+  std::vector<double2> gbuf;
+  for (const auto& g : h->gates_host)
+    for (const auto& z : g) gbuf.push_back(ptt::mk<double>(z.real(), z.imag()));
+  if (!check(hipMemcpyAsync(P.gates, gbuf.data(), gbuf.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "gates") ||
+      !check(hipStreamSynchronize(st), hp, "gates sync"))
+    return PT_TEBD_EDEVICE;
+  h->gates = P.gates;
+
+  // chain state: product initial state, Gamma_n[0][s][0][0] = vec(rho_n)[s]
+  for (int k = 0; k < 2; ++k) {
+    ChainDev& C = h->chain_host[k];
+    C.n_sites = N; C.chi_cap = c.chi_cap; C.xi_cap = c.xi_cap; C.gam_cap = c.gam_cap;
+    C.gam = P.gam[k]; C.parity = P.parity[k]; C.chi = P.chi[k]; C.xi = P.xi[k];
+    C.lam = P.lam[k]; C.log_scale = P.log_scale[k]; C.status = P.status[k];
+  }
+  {
+    std::vector<double2> g0((size_t)N * 2 * c.gam_cap, ptt::mk<double>(0.0, 0.0));
+    for (int n = 0; n < N; ++n)
+      for (int s2 = 0; s2 < 4; ++s2)
+        g0[(size_t)n * 2 * c.gam_cap + s2] = ptt::mk<double>(cfg->rho0[8 * n + 2 * s2], cfg->rho0[8 * n + 2 * s2 + 1]);
+    std::vector<int> zeros(N, 0), ones(N + 1, 1);
+    std::vector<double> lam((size_t)(N + 1) * c.chi_cap, 0.0);
+    for (int n = 0; n <= N; ++n) lam[(size_t)n * c.chi_cap] = 1.0;
+    double zero = 0.0;
+    int zi = 0;
+    bool ok = check(hipMemcpyAsync(P.gam[0], g0.data(), g0.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.parity[0], zeros.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.chi[0], ones.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.xi[0], ones.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.lam[0], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.log_scale[0], &zero, sizeof(double), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.status[0], &zi, sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.status[1], &zi, sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.chains, h->chain_host, 2 * sizeof(ChainDev), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipStreamSynchronize(st), hp, "init sync");
+    if (!ok) return PT_TEBD_EDEVICE;
+  }
+  h->chains = P.chains;
+
+  // baths: tensors, offsets, dims, caps (backward recursion when not given)
+  h->n_baths = cfg->n_baths;
+  h->bath_of_site_host.assign(N, -1);
+  h->pt_steps = 1 << 30;
+  std::vector<BathDev> bdev(std::max(cfg->n_baths, 1));
+  for (int i = 0; i < cfg->n_baths; ++i) {
+    const pt_tebd_bath& b = cfg->baths[i];
+    const int m = b.n_steps, per = b.diagonal ? 4 : 16;
+    h->pt_steps = std::min(h->pt_steps, m);
+    h->bath_of_site_host[b.site] = i;
+    std::vector<double2> tens;
+    std::vector<long long> toff(m);
+    std::vector<std::vector<cplx>> thost(m);
+    std::vector<int> dims(b.bond_dims, b.bond_dims + m + 1);
+    for (int k = 0; k < m; ++k) {
+      toff[k] = (long long)tens.size();
+      const long long len = (long long)dims[k] * dims[k + 1] * per;
+      thost[k].resize(len);
+      for (long long q = 0; q < len; ++q) {
+        tens.push_back(ptt::mk<double>(b.tensors[k][2 * q], b.tensors[k][2 * q + 1]));
+        thost[k][q] = {b.tensors[k][2 * q], b.tensors[k][2 * q + 1]};
+      }
+    }
+    std::vector<double2> caps;
+    std::vector<long long> coff(m + 1);
+    std::vector<std::vector<cplx>> chost;
+    if (!b.caps) chost = ptt::caps_backward(thost, dims, 2, b.diagonal != 0);
+    for (int k = 0; k <= m; ++k) {
+      coff[k] = (long long)caps.size();
+      for (int e = 0; e < dims[k]; ++e) {
+        if (b.caps) caps.push_back(ptt::mk<double>(b.caps[k][2 * e], b.caps[k][2 * e + 1]));
+        else caps.push_back(ptt::mk<double>(chost[k][e].real(), chost[k][e].imag()));
+      }
+    }
+    bool ok = check(hipMemcpyAsync(P.bath_tens[i], tens.data(), tens.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "bath") &&
+              check(hipMemcpyAsync(P.bath_toff[i], toff.data(), m * sizeof(long long), hipMemcpyHostToDevice, st), hp, "bath") &&
+              check(hipMemcpyAsync(P.bath_dims[i], dims.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, st), hp, "bath") &&
+              check(hipMemcpyAsync(P.bath_caps[i], caps.data(), caps.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "bath") &&
+              check(hipMemcpyAsync(P.bath_coff[i], coff.data(), (m + 1) * sizeof(long long), hipMemcpyHostToDevice, st), hp, "bath") &&
+              check(hipStreamSynchronize(st), hp, "bath sync");
+    if (!ok) return PT_TEBD_EDEVICE;
+    BathDev& bd = bdev[i];
+    bd.site = b.site; bd.n_steps = m; bd.diagonal = b.diagonal ? 1 : 0;
+    bd.tens = P.bath_tens[i]; bd.toff = P.bath_toff[i]; bd.dims = P.bath_dims[i];
+    bd.caps = P.bath_caps[i]; bd.coff = P.bath_coff[i];
+  }
+  if (cfg->n_baths == 0) h->pt_steps = 1 << 30;
+  if (!check(hipMemcpyAsync(P.baths, bdev.data(), bdev.size() * sizeof(BathDev), hipMemcpyHostToDevice, st), hp, "baths") ||
+      !check(hipMemcpyAsync(P.bath_of_site, h->bath_of_site_host.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "baths") ||
+      !check(hipStreamSynchronize(st), hp, "sync"))
+    return PT_TEBD_EDEVICE;
+  h->baths = P.baths;
+  h->bath_of_site = P.bath_of_site;
+  h->obs = P.obs;
+  h->ops_cap = 8 * N + 8;
+  h->ops_sites = P.ops_sites;
+  h->ops_vec = P.ops_vec;
+  h->ops_out = P.ops_out;
+  h->ops_log = P.ops_log;
+  h->site_op = P.site_op;
+
+  // sublayer job tables
+  for (int par = 0; par < 2; ++par) {
+    Sublayer& S = par == 0 ? h->sub_even : h->sub_odd;
+    for (int b = (par == 0 ? 1 : 0); b + 1 < N; b += 2) S.bonds.push_back(b);
+    const int n = (int)S.bonds.size();
+    S.jobs = P.jobs[par];
+    S.heev_b = P.hb[par];
+    S.heev_oy = P.hoy[par];
+    S.heev_oz = P.hoz[par];
+    S.heev_rr = P.hrr[par];
+    std::vector<HeevJob> hb2(2 * std::max(n, 1)), hoy(std::max(n, 1)), hoz(std::max(n, 1)), hrr(std::max(n, 1));
+    for (int i = 0; i < n; ++i) {
+      BondJob J = P.slots[i];
+      J.chain = 0;
+      J.bond = S.bonds[i];
+      J.gate = P.gates + (size_t)J.bond * 256;
+      J.chi_max = cfg->chi_max;
+      J.k_cap = c.kc;
+      J.eps = cfg->svd_rel_cutoff;
+      J.seed = ptt::splitmix64(cfg->seed ^ (0xA24BAED4963EE407ull * (unsigned long long)(J.bond + 1)));
+      J.nb_cap = c.nb;
+      J.dn_cap = c.dn;
+      S.host_jobs.push_back(J);
+      int* st0 = P.status[0];
+      fill_heev(hb2[2 * i], J.gl, c.nb, J.dims + ptt::D_NL, J.wl, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
+                P.h_z[0][i], c.nh, J.dims + ptt::D_L, ptt::RULE_EPS, J.eps, 0, nullptr, 0.0, J.vl, c.nb,
+                ptt::SCALE_NONE, st0);
+      fill_heev(hb2[2 * i + 1], J.gr, c.nb, J.dims + ptt::D_NR, J.wr, P.h_refl[1][i], P.h_tri[1][i], P.h_work[1][i],
+                P.h_z[1][i], c.nh, J.dims + ptt::D_R, ptt::RULE_EPS, J.eps, 0, nullptr, 0.0, J.vr, c.nb,
+                ptt::SCALE_NONE, st0);
+      fill_heev(hoy[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
+                P.h_z[0][i], c.nh, J.dims + ptt::D_KQ, ptt::RULE_RANK, 0.0, 0, nullptr, 1e-15, J.vk, c.kc,
+                ptt::SCALE_INV_SQRT, st0);
+      hoz[i] = hoy[i];
+      hoz[i].nvec_out = J.dims + ptt::D_KZ;
+      fill_heev(hrr[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
+                P.h_z[0][i], c.nh, J.dims + ptt::D_CHI, ptt::RULE_CAP, J.eps, cfg->chi_max, J.norms + 2, 0.0,
+                J.vk, c.kc, ptt::SCALE_NONE, st0);
+    }
+    if (n > 0) {
+      bool ok = check(hipMemcpyAsync(S.jobs, S.host_jobs.data(), n * sizeof(BondJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_b, hb2.data(), 2 * n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_oy, hoy.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_oz, hoz.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_rr, hrr.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipStreamSynchronize(st), hp, "jobs sync");
+      if (!ok) return PT_TEBD_EDEVICE;
+    }
+  }
+  *out = h.release();
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_step(pt_tebd_t h, int32_t n_steps) {
+  if (!h || n_steps < 0) return PT_TEBD_EINVAL;
+  if (h->n_baths > 0 && h->step + n_steps > h->pt_steps) {
+    h->err = "stepping past the end of a PT-MPO";
+    return PT_TEBD_ERANGE;
+  }
+  for (int i = 0; i < n_steps; ++i) {
+    step_chain(h, 0, h->step + 1);
+    ++h->step;
+  }
+  if (!check(hipGetLastError(), h, "kernel launch")) return PT_TEBD_EDEVICE;
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_observe(pt_tebd_t h, int32_t n_ops, const int32_t* sites, const double* ops, double* out,
+                               double* trace_out) {
+  if (!h || n_ops < 0 || (n_ops > 0 && (!sites || !ops || !out))) return PT_TEBD_EINVAL;
+  for (int i = 0; i < n_ops; ++i)
+    if (sites[i] < 0 || sites[i] >= h->n_sites) { h->err = "observable site out of range"; return PT_TEBD_EINVAL; }
+  // one extra trace request at site 0 so the trace is always available
+  std::vector<int> s2(sites, sites + n_ops);
+  std::vector<double> ov(8 * (n_ops + 1));
+  for (int i = 0; i < n_ops; ++i) obs_vector(ops + 8 * i, ov.data() + 8 * i);
+  s2.push_back(0);
+  const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  obs_vector(eye, ov.data() + 8 * n_ops);
+  std::vector<std::complex<double>> num, den;
+  std::vector<double> lg;
+  const pt_tebd_status s = observe_raw(h, 0, h->step, n_ops + 1, s2.data(), ov.data(), num, den, lg);
+  if (s != PT_TEBD_OK) return s;
+  for (int i = 0; i < n_ops; ++i) {
+    const std::complex<double> v = num[i] / den[i];
+    out[2 * i] = v.real();
+    out[2 * i + 1] = v.imag();
+  }
+  if (trace_out) {
+    const std::complex<double> t = std::exp(lg[n_ops]) * num[n_ops];
+    trace_out[0] = t.real();
+    trace_out[1] = t.imag();
+  }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a, int32_t site_b,
+                                 const double* op_b, int32_t n_steps, double* out) {
+  if (!h || !op_a || !op_b || !out || n_steps < 0) return PT_TEBD_EINVAL;
+  if (site_a < 0 || site_a >= h->n_sites || site_b < 0 || site_b >= h->n_sites) return PT_TEBD_EINVAL;
+  if (h->n_baths > 0 && h->step + n_steps > h->pt_steps) {
+    h->err = "correlation runs past the end of a PT-MPO";
+    return PT_TEBD_ERANGE;
+  }
+  // trace of the main state at the insertion time
+  const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  double ov[8];
+  obs_vector(eye, ov);
+  int s0 = 0;
+  std::vector<std::complex<double>> num, den;
+  std::vector<double> lg;
+  pt_tebd_status s = observe_raw(h, 0, h->step, 1, &s0, ov, num, den, lg);
+  if (s != PT_TEBD_OK) return s;
+  const std::complex<double> tr0 = num[0];
+  const double tr0_log = lg[0];
+  // fork: copy the whole main state into the second chain slot
+  const ChainDev& M = h->chain_host[0];
+  const ChainDev& F = h->chain_host[1];
+  const int N = h->n_sites;
+  const Caps& c = h->cap;
+  bool ok = check(hipMemcpyAsync(F.gam, M.gam, (size_t)N * 2 * c.gam_cap * sizeof(double2), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemcpyAsync(F.parity, M.parity, N * sizeof(int), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemcpyAsync(F.chi, M.chi, (N + 1) * sizeof(int), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemcpyAsync(F.xi, M.xi, N * sizeof(int), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemcpyAsync(F.lam, M.lam, (size_t)(N + 1) * c.chi_cap * sizeof(double), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemcpyAsync(F.log_scale, M.log_scale, sizeof(double), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
+            check(hipMemsetAsync(F.status, 0, sizeof(int), h->stream), h, "fork");
+  if (!ok) return PT_TEBD_EDEVICE;
+  // A acting from the left: (A kron 1) in the site Liouville space
+  std::vector<double2> sop(16);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k)
+        for (int l = 0; l < 2; ++l) {
+          double re = 0, im = 0;
+          if (j == l) { re = op_a[2 * (i * 2 + k)]; im = op_a[2 * (i * 2 + k) + 1]; }
+          sop[(i * 2 + j) * 4 + (k * 2 + l)] = ptt::mk<double>(re, im);
+        }
+  if (!check(hipMemcpyAsync(h->site_op, sop.data(), 16 * sizeof(double2), hipMemcpyHostToDevice, h->stream), h, "op"))
+    return PT_TEBD_EDEVICE;
+  ptt::k_apply_site_op<<<elem_blocks((long long)c.chi_cap * c.xi_cap * c.chi_cap), kThreads, 0, h->stream>>>(
+      h->chains + 1, site_a, h->site_op);
+  double obv[8];
+  obs_vector(op_b, obv);
+  for (int j = 0; j <= n_steps; ++j) {
+    if (j > 0) step_chain(h, 1, h->step + j);
+    s = observe_raw(h, 1, h->step + j, 1, &site_b, obv, num, den, lg);
+    if (s != PT_TEBD_OK) return s;
+    const std::complex<double> v = num[0] * std::exp(lg[0] - tr0_log) / tr0;
+    out[2 * j] = v.real();
+    out[2 * j + 1] = v.imag();
+  }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi) {
+  if (!h || !chi) return PT_TEBD_EINVAL;
+  const int N = h->n_sites;
+  std::vector<int> c(N + 1), x(N);
+  if (!check(hipMemcpyAsync(c.data(), h->chain_host[0].chi, (N + 1) * sizeof(int), hipMemcpyDeviceToHost, h->stream), h, "dims") ||
+      !check(hipMemcpyAsync(x.data(), h->chain_host[0].xi, N * sizeof(int), hipMemcpyDeviceToHost, h->stream), h, "dims") ||
+      !check(hipStreamSynchronize(h->stream), h, "sync"))
+    return PT_TEBD_EDEVICE;
+  for (int b = 0; b + 1 < N; ++b) chi[b] = c[b + 1];
+  if (xi)
+    for (int n = 0; n < N; ++n) xi[n] = x[n];
+  return device_status(h, 0);
+}
+
+pt_tebd_status pt_tebd_snapshot(pt_tebd_t h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return PT_TEBD_EINVAL;
+  const ChainDev& M = h->chain_host[0];
+  const int N = h->n_sites;
+  const Caps& c = h->cap;
+  const size_t need = sizeof(int) * 4 + (size_t)N * 2 * c.gam_cap * sizeof(double2) + N * sizeof(int) +
+                      (N + 1) * sizeof(int) + N * sizeof(int) + (size_t)(N + 1) * c.chi_cap * sizeof(double) +
+                      sizeof(double);
+  if (!buf) { *bytes = need; return PT_TEBD_OK; }
+  if (*bytes < need) { *bytes = need; return PT_TEBD_ENOMEM; }
+  char* p = static_cast<char*>(buf);
+  int hdr[4] = {0x50545442, N, (int)c.gam_cap, h->step};
+  std::memcpy(p, hdr, sizeof(hdr));
+  p += sizeof(hdr);
+  bool ok = true;
+  auto d2h = [&](void* dev, size_t len) {
+    ok = ok && check(hipMemcpyAsync(p, dev, len, hipMemcpyDeviceToHost, h->stream), h, "snapshot");
+    p += len;
+  };
+  d2h(M.gam, (size_t)N * 2 * c.gam_cap * sizeof(double2));
+  d2h(M.parity, N * sizeof(int));
+  d2h(M.chi, (N + 1) * sizeof(int));
+  d2h(M.xi, N * sizeof(int));
+  d2h(M.lam, (size_t)(N + 1) * c.chi_cap * sizeof(double));
+  d2h(M.log_scale, sizeof(double));
+  if (!ok || !check(hipStreamSynchronize(h->stream), h, "sync")) return PT_TEBD_EDEVICE;
+  *bytes = need;
+  return device_status(h, 0);
+}
+
+pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes) {
+  if (!h || !buf) return PT_TEBD_EINVAL;
+  const ChainDev& M = h->chain_host[0];
+  const int N = h->n_sites;
+  const Caps& c = h->cap;
+  const char* p = static_cast<const char*>(buf);
+  int hdr[4];
+  if (bytes < sizeof(hdr)) return PT_TEBD_EINVAL;
+  std::memcpy(hdr, p, sizeof(hdr));
+  if (hdr[0] != 0x50545442 || hdr[1] != N || hdr[2] != (int)c.gam_cap) { h->err = "snapshot does not match handle"; return PT_TEBD_EINVAL; }
+  p += sizeof(hdr);
+  bool ok = true;
+  auto h2d = [&](void* dev, size_t len) {
+    ok = ok && check(hipMemcpyAsync(dev, p, len, hipMemcpyHostToDevice, h->stream), h, "restore");
+    p += len;
+  };
+  h2d(M.gam, (size_t)N * 2 * c.gam_cap * sizeof(double2));
+  h2d(M.parity, N * sizeof(int));
+  h2d(M.chi, (N + 1) * sizeof(int));
+  h2d(M.xi, N * sizeof(int));
+  h2d(M.lam, (size_t)(N + 1) * c.chi_cap * sizeof(double));
+  h2d(M.log_scale, sizeof(double));
+  if (!ok || !check(hipStreamSynchronize(h->stream), h, "sync")) return PT_TEBD_EDEVICE;
+  h->step = hdr[3];
+  return PT_TEBD_OK;
+}
+
+int32_t pt_tebd_current_step(pt_tebd_t h) { return h ? h->step : -1; }
+
+const char* pt_tebd_last_error(pt_tebd_t h) { return h ? h->err.c_str() : "null handle"; }
+
+void pt_tebd_destroy(pt_tebd_t h) {
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps) {
+  if (!hs || n < 0 || n_steps < 0) return PT_TEBD_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    const pt_tebd_status s = pt_tebd_step(hs[i], n_steps);
+    if (s != PT_TEBD_OK) return s;
+  }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_gate(pt_tebd_t h, int32_t bond, double* out) {
+  if (!h || !out || bond < 0 || bond >= (int)h->gates_host.size()) return PT_TEBD_EINVAL;
+  const auto& g = h->gates_host[bond];
+  for (size_t i = 0; i < g.size(); ++i) {
+    out[2 * i] = g[i].real();
+    out[2 * i + 1] = g[i].imag();
+  }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_bath_eta(double alpha, double wc, int32_t cutoff_kind, double temperature, double dt,
+                           int32_t mem_steps, double* eta_out) {
+  if (!eta_out) return PT_TEBD_EINVAL;
+  std::vector<cplx> eta;
+  std::string err;
+  if (!ptt::bath_eta(alpha, wc, cutoff_kind, temperature, dt, mem_steps, eta, err)) return PT_TEBD_EINVAL;
+  for (size_t i = 0; i < eta.size(); ++i) {
+    eta_out[2 * i] = eta[i].real();
+    eta_out[2 * i + 1] = eta[i].imag();
+  }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_mpo_build_ohmic(double alpha, double wc, int32_t cutoff_kind, double temperature, double dt,
+                                  int32_t n_steps, int32_t mem_steps, double eps, int32_t xi_max,
+                                  const double* coupling_op, int32_t d, pt_tebd_bath* out) {
+  if (!out || !coupling_op || d != 2 || n_steps < 1 || mem_steps < 0 || xi_max < 1 || !(eps >= 0.0))
+    return PT_TEBD_EINVAL;
+  std::vector<cplx> eta;
+  std::string err;
+  if (!ptt::bath_eta(alpha, wc, cutoff_kind, temperature, dt, mem_steps, eta, err)) return PT_TEBD_EINVAL;
+  // coupling eigenbasis: keep the computational basis when diagonal
+  cplx s[4];
+  for (int i = 0; i < 4; ++i) s[i] = {coupling_op[2 * i], coupling_op[2 * i + 1]};
+  if (std::abs(s[1] - std::conj(s[2])) > 1e-12 || std::abs(s[0].imag()) > 1e-12 || std::abs(s[3].imag()) > 1e-12)
+    return PT_TEBD_EINVAL;
+  const bool diag = std::abs(s[1]) == 0.0 && std::abs(s[2]) == 0.0;
+  std::vector<double> sigma(2);
+  std::vector<cplx> u(4, 0.0);
+  if (diag) {
+    sigma = {s[0].real(), s[3].real()};
+    u[0] = u[3] = 1.0;
+  } else {
+    double w[2];
+    ptt::heev(2, s, w, u.data());
+    sigma = {w[0], w[1]};
+  }
+  std::vector<std::vector<cplx>> tens;
+  std::vector<int> dims;
+  if (!ptt::build_ptmpo(eta, sigma, n_steps, eps, xi_max, tens, dims, err)) return PT_TEBD_EINVAL;
+  out->site = 0;
+  out->n_steps = n_steps;
+  out->diagonal = diag ? 1 : 0;
+  int32_t* bd = static_cast<int32_t*>(std::malloc(sizeof(int32_t) * (n_steps + 1)));
+  const double** tp = static_cast<const double**>(std::malloc(sizeof(double*) * n_steps));
+  if (!bd || !tp) return PT_TEBD_ENOMEM;
+  for (int k = 0; k <= n_steps; ++k) bd[k] = dims[k];
+  // W = U kron conj(U): eigenbasis vec -> computational vec
+  cplx wmat[16];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k)
+        for (int l = 0; l < 2; ++l) wmat[(i * 2 + j) * 4 + (k * 2 + l)] = u[i * 2 + k] * std::conj(u[j * 2 + l]);
+  for (int k = 0; k < n_steps; ++k) {
+    const int xa = dims[k], xb = dims[k + 1];
+    const size_t per = diag ? 4 : 16;
+    double* t = static_cast<double*>(std::malloc(sizeof(double) * 2 * per * xa * xb));
+    if (!t) return PT_TEBD_ENOMEM;
+    for (int e = 0; e < xa; ++e)
+      for (int f = 0; f < xb; ++f) {
+        const cplx* p = &tens[k][((size_t)e * xb + f) * 4];
+        if (diag) {
+          for (int x = 0; x < 4; ++x) {
+            t[2 * (((size_t)e * xb + f) * 4 + x)] = p[x].real();
+            t[2 * (((size_t)e * xb + f) * 4 + x) + 1] = p[x].imag();
+          }
+        } else {
+          for (int so = 0; so < 4; ++so)
+            for (int si = 0; si < 4; ++si) {
+              cplx acc = 0.0;
+              for (int x = 0; x < 4; ++x) acc += wmat[so * 4 + x] * p[x] * std::conj(wmat[si * 4 + x]);
+              const size_t q = (((size_t)e * xb + f) * 4 + so) * 4 + si;
+              t[2 * q] = acc.real();
+              t[2 * q + 1] = acc.imag();
+            }
+        }
+      }
+    tp[k] = t;
+  }
+  out->bond_dims = bd;
+  out->tensors = tp;
+  out->caps = nullptr;
+  return PT_TEBD_OK;
+}
+
+void pt_mpo_free(pt_tebd_bath* b) {
+  if (!b) return;
+  if (b->tensors)
+    for (int k = 0; k < b->n_steps; ++k) std::free(const_cast<double*>(b->tensors[k]));
+  std::free(const_cast<double**>(b->tensors));
+  std::free(const_cast<int32_t*>(b->bond_dims));
+  b->tensors = nullptr;
+  b->bond_dims = nullptr;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ test hooks
+#include "pt_tebd_testing.h"
+
+extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
+                                       double* w, double* v, int32_t* nvec) {
+  if (n < 1 || n > 1024 || !a || !w || !v || !nvec) return PT_TEBD_EINVAL;
+  const size_t nn = (size_t)n * n;
+  double2 *da = nullptr, *drefl = nullptr, *dv = nullptr;
+  double *dw = nullptr, *dtri = nullptr, *dwork = nullptr, *dz = nullptr, *dextra = nullptr;
+  int *dn = nullptr, *dnvec = nullptr, *dstat = nullptr;
+  HeevJob* djob = nullptr;
+  bool ok = hipMalloc(&da, nn * sizeof(double2)) == hipSuccess && hipMalloc(&drefl, nn * sizeof(double2)) == hipSuccess &&
+            hipMalloc(&dv, nn * sizeof(double2)) == hipSuccess && hipMalloc(&dw, n * sizeof(double)) == hipSuccess &&
+            hipMalloc(&dtri, 6 * n * sizeof(double)) == hipSuccess && hipMalloc(&dwork, 8 * nn * sizeof(double)) == hipSuccess &&
+            hipMalloc(&dz, nn * sizeof(double)) == hipSuccess && hipMalloc(&dextra, sizeof(double)) == hipSuccess &&
+            hipMalloc(&dn, sizeof(int)) == hipSuccess && hipMalloc(&dnvec, sizeof(int)) == hipSuccess &&
+            hipMalloc(&dstat, sizeof(int)) == hipSuccess && hipMalloc(&djob, sizeof(HeevJob)) == hipSuccess;
+  pt_tebd_status st = PT_TEBD_OK;
+  if (ok) {
+    HeevJob J{};
+    const int r = rule == 0 ? ptt::RULE_ALL : rule == 1 ? ptt::RULE_EPS : rule == 2 ? ptt::RULE_CAP : ptt::RULE_RANK;
+    fill_heev(J, da, n, dn, dw, drefl, dtri, dwork, dz, n, dnvec, r, eps, cap, dextra, eps, dv, n, ptt::SCALE_NONE, dstat);
+    const double zero = 0.0;
+    const int zi = 0;
+    ok = hipMemcpy(da, a, nn * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dn, &n, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dextra, &zero, sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dstat, &zi, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(djob, &J, sizeof(HeevJob), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(dv, 0, nn * sizeof(double2)) == hipSuccess;
+    if (ok) {
+      launch_heev(nullptr, djob, 1, n);
+      ok = hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess &&
+           hipMemcpy(w, dw, n * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipMemcpy(v, dv, nn * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipMemcpy(nvec, dnvec, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+  }
+  if (!ok) st = PT_TEBD_EDEVICE;
+  hipFree(da); hipFree(drefl); hipFree(dv); hipFree(dw); hipFree(dtri); hipFree(dwork); hipFree(dz);
+  hipFree(dextra); hipFree(dn); hipFree(dnvec); hipFree(dstat); hipFree(djob);
+  return st;
+}

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same inputs (the oracle's PT-MPO tensors and caps feed both paths).
+
+Tolerance (stated requirement for the double-precision path): every
+observable within 1e-6 of the oracle.  Small untruncated cases are held to
+tighter bounds where the arithmetic allows it (noted per test).
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gates as ogates
+from oracle import pt_tebd as opt
+from paper_2201_05529_amd import workloads as W
+from tests.conftest import gpu_available
+from tests.helpers import ROOT, ensure_library, library_chain, oracle_problem, run_both
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-6
+SZ, SX, SY = W.SZ, W.SX, W.SY
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    ensure_library()
+
+
+def _heev(n, a, rule=0, eps=0.0, cap=0):
+    from paper_2201_05529_amd import binding as B
+    L = B.lib()
+    L.pt_test_heev.restype = ctypes.c_int
+    af = B._cplx(a)
+    w = np.zeros(n)
+    v = np.zeros(2 * n * n)
+    nv = ctypes.c_int32()
+    st = L.pt_test_heev(n, B._dptr(af), rule, ctypes.c_double(eps), cap, B._dptr(w), B._dptr(v), ctypes.byref(nv))
+    assert st == 0
+    return w, v.view(np.complex128).reshape(n, n), nv.value
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 64, 100, 256])
+def test_heev_random_hermitian(n):
+    print(f"heev n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    m = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    a = m + m.conj().T
+    w, v, nv = _heev(n, a, rule=0)
+    ref = np.sort(np.linalg.eigvalsh(a))[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() < 1e-12 * scale * max(n, 1)
+    k = nv
+    assert k == int(np.count_nonzero(ref > 0))
+    vk = v[:, :k]
+    res = a @ vk - vk * w[:k]
+    assert np.abs(res).max() < 1e-10 * scale
+    assert np.abs(vk.conj().T @ vk - np.eye(k)).max() < 1e-10
+
+
+def test_heev_gram_with_degeneracy_and_rank_deficiency():
+    # a Gram matrix with an exactly degenerate pair and a null space, as the
+    # truncated SVDs see them
+    rng = np.random.default_rng(7)
+    q, _ = np.linalg.qr(rng.normal(size=(40, 40)) + 1j * rng.normal(size=(40, 40)))
+    lam = np.zeros(40)
+    lam[:12] = [5.0, 3.0, 3.0, 1.0, 0.5, 0.5, 0.5, 1e-3, 1e-5, 1e-7, 1e-9, 1e-11]
+    a = (q * lam) @ q.conj().T
+    w, v, nv = _heev(40, a, rule=1, eps=1e-7)
+    ref = np.sort(lam)[::-1]
+    assert np.abs(w - ref).max() < 1e-13 * 5.0 * 40
+    # eps rule on sigma = sqrt(lambda): dropping lambda = 1e-11 leaves a tail
+    # of 3e-6 > 1e-7 * sigma_1, so every eigenvalue above round-off is kept
+    assert nv == 12
+    vk = v[:, :10]   # vectors with lambda >= 1e-7 * lambda_1 are well determined
+    assert np.abs(vk.conj().T @ vk - np.eye(10)).max() < 1e-9
+    # projector onto the degenerate triple is well defined
+    p_gpu = vk[:, 4:7] @ vk[:, 4:7].conj().T
+    p_ref = q[:, 4:7] @ q[:, 4:7].conj().T
+    assert np.abs(p_gpu - p_ref).max() < 1e-9
+
+
+def test_gates_match_oracle():
+    wl = W.random_small_chain(3, 5)
+    wl["lindblad"] = [[0.2 * SZ], [], [0.1 * (SX - 1j * SY) / 2], [], [0.3 * SX]]
+    prob = oracle_problem(wl, n_steps=2)
+    ch = library_chain(wl, prob)
+    ref = ogates.chain_gates(wl["h_site"], wl["h_bond"], wl["lindblad"], wl["dt"], 2)
+    for b in range(4):
+        assert np.abs(ch.gate(b) - ref[b]).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_zero_coupling_matches_oracle(n):
+    print(f"zero coupling n={n}", flush=True)
+    wl = W.random_small_chain(100 + n, n, with_bath_sites=(), eps=1e-12)
+    ops = [(s, op) for s in range(n) for op in (SX, SY, SZ)]
+    g, o, gt, ot, ch, eng = run_both(wl, 6, ops)
+    assert np.abs(g - o).max() < 1e-9
+    assert np.abs(gt - 1.0).max() < 1e-10
+
+
+@pytest.mark.parametrize("n,sites", [(1, (0,)), (2, (0, 1)), (3, (1,)), (4, (0, 3)), (5, (0, 2, 4))])
+def test_small_chains_with_baths_match_oracle(n, sites):
+    print(f"baths n={n} sites={sites}", flush=True)
+    wl = W.random_small_chain(200 + n, n, with_bath_sites=sites, k_cut=3, eps=1e-10, xi_max=64)
+    ops = [(s, op) for s in range(n) for op in (SX, SZ)]
+    g, o, gt, ot, ch, eng = run_both(wl, 8, ops)
+    err = np.abs(g - o).max()
+    print(f"  max |d<O>| = {err:.2e}", flush=True)
+    assert err < FP64_TOL
+    assert np.abs(gt - ot).max() < FP64_TOL * np.abs(ot).max()
+
+
+def test_xyz3_workload_matches_oracle():
+    wl = W.xyz3()
+    print("xyz3 40 steps", flush=True)
+    ops = [(s, SZ) for s in range(3)] + [(0, SX), (1, SY)]
+    g, o, gt, ot, ch, eng = run_both(wl, wl["n_steps"], ops)
+    errs = np.abs(g - o).max(axis=0)
+    print("  per-observable max error", errs, flush=True)
+    assert errs.max() < FP64_TOL
+    assert np.abs(gt - ot).max() < FP64_TOL
+    assert np.abs(g.imag).max() < 1e-6
+
+
+def test_xyz5_workload_and_correlation_match_oracle():
+    wl = W.xyz5()
+    n_steps = 60
+    print(f"xyz5 {n_steps} steps", flush=True)
+    ops = [(s, SZ) for s in range(5)]
+    prob = oracle_problem(wl, n_steps=wl["n_steps"])
+    eng = opt.Engine(prob)
+    ch = library_chain(wl, prob)
+    # two-time correlation <sigma^x_1(t) sigma^x_1(0)> from the initial state
+    c_gpu = ch.correlate(0, SX, 0, SX, 30)
+    c_ref = eng.correlate(0, SX, 0, SX, 30)
+    print("  correlation max error", np.abs(c_gpu - c_ref).max(), flush=True)
+    assert np.abs(c_gpu - c_ref).max() < FP64_TOL
+    assert ch.current_step == 0
+    errs = []
+    for k in range(n_steps + 1):
+        if k:
+            ch.step(1)
+            eng.step(1)
+        v, tr = ch.observe([s for s, _ in ops], np.array([op for _, op in ops]))
+        ref = np.array([eng.expectation(s, op) for s, op in ops])
+        errs.append(np.abs(v - ref).max())
+        assert abs(tr - eng.trace()) < FP64_TOL
+    print("  max <sz> error", max(errs), flush=True)
+    assert max(errs) < FP64_TOL
+
+
+def test_snapshot_restore_is_bit_identical():
+    wl = W.random_small_chain(300, 4, with_bath_sites=(0, 3), k_cut=3, eps=1e-8, xi_max=32)
+    prob = oracle_problem(wl, n_steps=8)
+    ch = library_chain(wl, prob)
+    ch.step(3)
+    snap = ch.snapshot()
+    ops = np.array([SZ] * 4)
+    ch.step(3)
+    a, ta = ch.observe(range(4), ops)
+    ch.restore(snap)
+    assert ch.current_step == 3
+    ch.step(3)
+    b, tb = ch.observe(range(4), ops)
+    assert np.array_equal(a, b) and ta == tb
+
+
+def test_deterministic_replay():
+    wl = W.random_small_chain(301, 5, with_bath_sites=(1, 3), k_cut=3, eps=1e-8, xi_max=32)
+    prob = oracle_problem(wl, n_steps=6)
+    vals = []
+    for _ in range(2):
+        ch = library_chain(wl, prob)
+        ch.step(6)
+        vals.append(ch.observe(range(5), np.array([SX] * 5))[0])
+        ch.close()
+    assert np.array_equal(vals[0], vals[1])
+
+
+def test_pt_range_error():
+    from paper_2201_05529_amd import binding as B
+    wl = W.random_small_chain(302, 3, with_bath_sites=(0,), k_cut=2)
+    prob = oracle_problem(wl, n_steps=3)
+    ch = library_chain(wl, prob)
+    ch.step(3)
+    with pytest.raises(B.PtTebdError) as e:
+        ch.step(1)
+    assert e.value.status == -6
