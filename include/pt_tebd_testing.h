@@ -18,7 +18,7 @@ extern "C" {
  * reduction, bisection, inverse iteration, back-transformation) on one n x n
  * Hermitian matrix a (complex, row-major, n <= 1024).  rule: 0 every positive
  * eigenvalue, 1 the eps rule on sqrt(eigenvalues), 2 the eps rule plus the
- * cap, 3 numerical rank (lambda_k > eps * lambda_0).  Returns the eigenvalues
+ * cap, 3 numerical rank (lambda_k > eps * lambda_0), 4 every eigenpair.  Returns the eigenvalues
  * in w[n] (descending), the selected eigenvectors in v (complex, row-major
  * n x n, column k = vector k) and their number in *nvec. */
 pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,

@@ -141,8 +141,14 @@ class Chain:
         cfg.n_sites, cfg.d, cfg.dt = n_sites, 2, float(dt)
         cfg.h_site, cfg.h_bond, cfg.rho0 = _dptr(hs), _dptr(hb), _dptr(r0)
         if lindblad is not None:
-            n_l = len(lindblad[0])
-            ld = _cplx(np.asarray(lindblad).reshape(n_sites, n_l, 2, 2))
+            # the ABI takes the same number of GKSL operators per site: pad
+            # ragged per-site lists with zero operators
+            n_l = max(len(ops) for ops in lindblad)
+            full = np.zeros((n_sites, max(n_l, 1), 2, 2), dtype=np.complex128)
+            for s_, ops in enumerate(lindblad):
+                for k_, op in enumerate(ops):
+                    full[s_, k_] = op
+            ld = _cplx(full)
             self._keep.append(ld)
             cfg.n_lindblad, cfg.lindblad = n_l, _dptr(ld)
         else:

@@ -9,13 +9,19 @@
 //   pack      B_L = lam_{n-1} Gamma_n as (a,e) x (s,b);  B_R = Gamma_{n+1} lam_{n+1}
 //             as (b,t) x (f,c)                                          (c)-(d)
 //   gram      G_L, G_R on the smaller side of each matrix
-//   heev      eigenpairs; the eps rule gives the ranks l, r             (d)-(e)
+//   heev      all eigenpairs of each Gram matrix
+//   prod      B_L V_L (or U_L^H B_L), U_R^H B_R (or B_R V_R): the singular
+//             values are the column (row) norms of these products, which
+//             resolves them to working precision relative to themselves
+//             (the square roots of Gram eigenvalues would only resolve them
+//             to ~1e-8 of the largest); the eps rule on them gives l, r (d)-(e)
 //   xy        X = S_L V_L^H (l x (s,b)) times lam_n on b;  Y = U_R S_R
 //   p, gate   P[(l,s),(t,r)] = sum_b X Y;  D = G applied on (s,t)       (e)-(f)
 //   rf        randomised range finder for the leading singular subspace of D
 //             (Gaussian sketch, power iteration, orthonormalisation by the
 //             eigendecomposition of the basis Gram matrix), Rayleigh-Ritz on
-//             Q^H D with the eps rule, the chi_max cap and the tie rule  (f)-(g)
+//             Q^H D (singular values again as row norms of W^H Q^H D) with
+//             the eps rule, the chi_max cap and the tie rule            (f)-(g)
 //   rebuild   Gamma_n' = lam_{n-1}^-1 U_L U^D,  Gamma_{n+1}' = V^D^H V_R^H
 //             lam_{n+1}^-1; where the eigenvectors sit on the far side of B
 //             the same products are evaluated as B V S^-1 U^D (resp.
@@ -26,6 +32,7 @@
 #include "device_common.h"
 #include "gemm.h"
 #include "heev.h"
+#include "refine.h"
 
 namespace ptt {
 
@@ -56,6 +63,7 @@ enum Dim : int {
   D_L, D_R, D_M, D_N,          // ranks l, r; D is M x N = 4l x 4r
   D_K, D_KQ, D_KZ, D_GS,       // sketch width, basis widths, current Gram size
   D_CHI,                       // new bond dimension
+  D_RF,                        // 1: randomised range finder active; 0: Q = identity (M <= sketch cap)
   D_COUNT
 };
 
@@ -71,10 +79,14 @@ struct BondJob {
   unsigned long long seed;
   int nb_cap;              // capacity of B Gram sizes (4 chi_cap); ld of gl/gr/vl/vr
   int dn_cap;              // capacity of M, N (4 nb_cap)
+  int ldr;                 // leading dim of pr (max(xi_cap chi_cap, nb_cap))
   int* dims;               // [D_COUNT]
   double* norms;           // [4]: ||D||_F^2, ||Q^H D||_F^2, extra tail, spare
   double2 *bl, *br, *gl, *gr, *vl, *vr, *x, *y, *p, *d;
   double *wl, *wr, *wk;
+  double *sl, *sr, *sk;    // singular values (norms) for B_L, B_R, D
+  double2 *pl, *pr;        // B_L V_L or U_L^H B_L;  U_R^H B_R or B_R V_R
+  double2 *tpl, *tvl, *tpr, *tvr;  // refinement temporaries
   double2 *omega, *ya, *yb, *za, *zb, *gk, *vk, *bm, *ud, *vdh, *t1, *tg;
 };
 
@@ -116,7 +128,8 @@ __global__ void k_pack(const ChainDev* chains, const BondJob* jobs) {
 // ------------------------------------------------------- batched products
 enum GemmKind : int {
   GK_GRAM_B = 0,   // sub 0: G_L, sub 1: G_R
-  GK_XY,           // sub 0: X = U_L^H B_L (rows side), sub 1: Y = B_R V_R (cols side)
+  GK_PROD_B,       // sub 0: pl = B_L V_L (side 0) | U_L^H B_L (side 1)
+                   // sub 1: pr = U_R^H B_R (side 0) | B_R V_R (side 1)
   GK_P,            // P = X' Y'
   GK_SKETCH,       // ya = D omega                     (M x K)
   GK_GRAM_YA,      // gk = ya^H ya                     (GS x GS)
@@ -130,13 +143,12 @@ enum GemmKind : int {
   GK_APPLY_ZB,     // za = zb vk                       (N x KZ)
   GK_D_Z,          // ya = D za                        (M x KZ)
   GK_QH_D,         // bm = ya^H D                      (KQ x N)
+  GK_RESID,        // p -= ya bm (p holds a copy of D) (M x N), only if K < min(M, N)
   GK_GRAM_BM,      // gk = bm bm^H                     (KQ x KQ)
+  GK_C,            // vdh = vk^H bm                    (KQ x N) = S V^D^H
   GK_UD,           // ud = ya vk                       (M x CHI)
-  GK_VDH,          // vdh = vk^H bm                    (CHI x N)
-  GK_T1,           // side-0 left: t1 = V_L (S^-1 U^D')
-  GK_NEWL,         // tg = B_L t1 (side 0) or U_L U^D' (side 1)
-  GK_T2,           // side-0 right: t1 = (V^D' S^-1) U_R^H
-  GK_NEWR,         // tg = t1 B_R (side 0) or V^D' V_R^H (side 1)
+  GK_NEWL,         // tg = pl (S^-1 ud') (side 0) | U_L ud' (side 1)      (rl x 4 chi)
+  GK_NEWR,         // tg = (vdh' S^-1) pr (side 0) | vdh' V_R^H (side 1) (4 chi x cr)
 };
 
 struct GemmArgs {
@@ -144,99 +156,111 @@ struct GemmArgs {
   const double2* B; int ldb; bool cb;
   double2* C; int ldc;
   int m, n, k;
+  double alpha;
+  bool acc;
 };
 
 __device__ inline bool gemm_args(const BondJob& J, int kind, int sub, GemmArgs& g) {
   const int* D = J.dims;
   const int kc = J.k_cap, nb = J.nb_cap;
+  g.alpha = 1.0;
+  g.acc = false;
+  auto set = [&](const double2* A, int lda, bool ca, const double2* B, int ldb, bool cb, double2* C, int ldc,
+                 int m, int n, int k) {
+    g.A = A; g.lda = lda; g.ca = ca; g.B = B; g.ldb = ldb; g.cb = cb; g.C = C; g.ldc = ldc;
+    g.m = m; g.n = n; g.k = k;
+  };
+  // the sketch / orthonormalisation / power-iteration products run only
+  // when the range finder is active
+  if (kind >= GK_SKETCH && kind <= GK_D_Z && D[D_RF] == 0) return false;
   switch (kind) {
     case GK_GRAM_B:
       if (sub == 0) {
         const int rl = D[D_RL], cl = D[D_CL];
-        if (D[D_SL] == 0) g = {J.bl, cl, true, J.bl, cl, false, J.gl, nb, cl, cl, rl};
-        else g = {J.bl, cl, false, J.bl, cl, true, J.gl, nb, rl, rl, cl};
+        if (D[D_SL] == 0) set(J.bl, cl, true, J.bl, cl, false, J.gl, nb, cl, cl, rl);
+        else set(J.bl, cl, false, J.bl, cl, true, J.gl, nb, rl, rl, cl);
       } else {
         const int rr = D[D_RR], cr = D[D_CR];
-        if (D[D_SR] == 0) g = {J.br, cr, false, J.br, cr, true, J.gr, nb, rr, rr, cr};
-        else g = {J.br, cr, true, J.br, cr, false, J.gr, nb, cr, cr, rr};
+        if (D[D_SR] == 0) set(J.br, cr, false, J.br, cr, true, J.gr, nb, rr, rr, cr);
+        else set(J.br, cr, true, J.br, cr, false, J.gr, nb, cr, cr, rr);
       }
       return true;
-    case GK_XY:
+    case GK_PROD_B:
       if (sub == 0) {
-        if (D[D_SL] != 1) return false;
-        g = {J.vl, nb, true, J.bl, D[D_CL], false, J.x, D[D_CL], D[D_L], D[D_CL], D[D_RL]};
+        const int rl = D[D_RL], cl = D[D_CL], n = D[D_NL];
+        if (D[D_SL] == 0) set(J.bl, cl, false, J.vl, nb, false, J.pl, nb, rl, n, cl);   // rl x n
+        else set(J.vl, nb, true, J.bl, cl, false, J.pl, nb, n, cl, rl);                 // n x cl
       } else {
-        if (D[D_SR] != 1) return false;
-        g = {J.br, D[D_CR], false, J.vr, nb, false, J.y, D[D_R], D[D_RR], D[D_R], D[D_CR]};
+        const int rr = D[D_RR], cr = D[D_CR], n = D[D_NR];
+        if (D[D_SR] == 0) set(J.vr, nb, true, J.br, cr, false, J.pr, J.ldr, n, cr, rr); // n x cr
+        else set(J.br, cr, false, J.vr, nb, false, J.pr, J.ldr, rr, n, cr);            // rr x n
       }
       return true;
     case GK_P:
-      g = {J.x, D[D_B], false, J.y, 4 * D[D_R], false, J.p, 4 * D[D_R], 4 * D[D_L], 4 * D[D_R], D[D_B]};
+      set(J.x, D[D_B], false, J.y, 4 * D[D_R], false, J.p, 4 * D[D_R], 4 * D[D_L], 4 * D[D_R], D[D_B]);
       return true;
     case GK_SKETCH:
-      g = {J.d, D[D_N], false, J.omega, kc, false, J.ya, kc, D[D_M], D[D_K], D[D_N]};
+      set(J.d, D[D_N], false, J.omega, kc, false, J.ya, kc, D[D_M], D[D_K], D[D_N]);
       return true;
     case GK_GRAM_YA:
-      g = {J.ya, kc, true, J.ya, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_M]};
+      set(J.ya, kc, true, J.ya, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_M]);
       return true;
     case GK_APPLY_YA:
-      g = {J.ya, kc, false, J.vk, kc, false, J.yb, kc, D[D_M], D[D_KQ], D[D_GS]};
+      set(J.ya, kc, false, J.vk, kc, false, J.yb, kc, D[D_M], D[D_KQ], D[D_GS]);
       return true;
     case GK_GRAM_YB:
-      g = {J.yb, kc, true, J.yb, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_M]};
+      set(J.yb, kc, true, J.yb, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_M]);
       return true;
     case GK_APPLY_YB:
-      g = {J.yb, kc, false, J.vk, kc, false, J.ya, kc, D[D_M], D[D_KQ], D[D_GS]};
+      set(J.yb, kc, false, J.vk, kc, false, J.ya, kc, D[D_M], D[D_KQ], D[D_GS]);
       return true;
     case GK_DH_Q:
-      g = {J.d, D[D_N], true, J.ya, kc, false, J.za, kc, D[D_N], D[D_KQ], D[D_M]};
+      set(J.d, D[D_N], true, J.ya, kc, false, J.za, kc, D[D_N], D[D_KQ], D[D_M]);
       return true;
     case GK_GRAM_ZA:
-      g = {J.za, kc, true, J.za, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_N]};
+      set(J.za, kc, true, J.za, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_N]);
       return true;
     case GK_APPLY_ZA:
-      g = {J.za, kc, false, J.vk, kc, false, J.zb, kc, D[D_N], D[D_KZ], D[D_GS]};
+      set(J.za, kc, false, J.vk, kc, false, J.zb, kc, D[D_N], D[D_KZ], D[D_GS]);
       return true;
     case GK_GRAM_ZB:
-      g = {J.zb, kc, true, J.zb, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_N]};
+      set(J.zb, kc, true, J.zb, kc, false, J.gk, kc, D[D_GS], D[D_GS], D[D_N]);
       return true;
     case GK_APPLY_ZB:
-      g = {J.zb, kc, false, J.vk, kc, false, J.za, kc, D[D_N], D[D_KZ], D[D_GS]};
+      set(J.zb, kc, false, J.vk, kc, false, J.za, kc, D[D_N], D[D_KZ], D[D_GS]);
       return true;
     case GK_D_Z:
-      g = {J.d, D[D_N], false, J.za, kc, false, J.ya, kc, D[D_M], D[D_KZ], D[D_N]};
+      set(J.d, D[D_N], false, J.za, kc, false, J.ya, kc, D[D_M], D[D_KZ], D[D_N]);
       return true;
     case GK_QH_D:
-      g = {J.ya, kc, true, J.d, D[D_N], false, J.bm, D[D_N], D[D_KQ], D[D_N], D[D_M]};
+      set(J.ya, kc, true, J.d, D[D_N], false, J.bm, D[D_N], D[D_KQ], D[D_N], D[D_M]);
+      return true;
+    case GK_RESID:
+      if (D[D_K] >= min(D[D_M], D[D_N])) return false;
+      set(J.ya, kc, false, J.bm, D[D_N], false, J.p, D[D_N], D[D_M], D[D_N], D[D_KQ]);
+      g.alpha = -1.0;
+      g.acc = true;
       return true;
     case GK_GRAM_BM:
-      g = {J.bm, D[D_N], false, J.bm, D[D_N], true, J.gk, kc, D[D_KQ], D[D_KQ], D[D_N]};
+      set(J.bm, D[D_N], false, J.bm, D[D_N], true, J.gk, kc, D[D_KQ], D[D_KQ], D[D_N]);
+      return true;
+    case GK_C:
+      set(J.vk, kc, true, J.bm, D[D_N], false, J.vdh, D[D_N], D[D_KQ], D[D_N], D[D_KQ]);
       return true;
     case GK_UD:
-      g = {J.ya, kc, false, J.vk, kc, false, J.ud, D[D_CHI], D[D_M], D[D_CHI], D[D_KQ]};
-      return true;
-    case GK_VDH:
-      g = {J.vk, kc, true, J.bm, D[D_N], false, J.vdh, D[D_N], D[D_CHI], D[D_N], D[D_KQ]};
-      return true;
-    case GK_T1:  // side 0: t1 (cl x 4chi) = V_L (cl x l) ud' (l x 4chi)
-      if (D[D_SL] != 0) return false;
-      g = {J.vl, nb, false, J.ud, 4 * D[D_CHI], false, J.t1, 4 * D[D_CHI], D[D_CL], 4 * D[D_CHI], D[D_L]};
+      set(J.ya, kc, false, J.vk, kc, false, J.ud, D[D_CHI], D[D_M], D[D_CHI], D[D_KQ]);
       return true;
     case GK_NEWL:
-      if (D[D_SL] == 0)  // tg (rl x 4chi) = B_L (rl x cl) t1
-        g = {J.bl, D[D_CL], false, J.t1, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_CL]};
-      else               // tg = U_L (rl x l) ud' (l x 4chi)
-        g = {J.vl, nb, false, J.ud, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_L]};
-      return true;
-    case GK_T2:  // side 0: t1 (4chi x rr) = vdh' (4chi x r) U_R^H (r x rr)
-      if (D[D_SR] != 0) return false;
-      g = {J.vdh, D[D_R], false, J.vr, nb, true, J.t1, D[D_RR], 4 * D[D_CHI], D[D_RR], D[D_R]};
+      if (D[D_SL] == 0)  // tg (rl x 4chi) = (B_L V_L)[:, :l] (S^-1 ud')
+        set(J.pl, nb, false, J.ud, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_L]);
+      else               // tg = U_L[:, :l] ud'
+        set(J.vl, nb, false, J.ud, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_L]);
       return true;
     case GK_NEWR:
-      if (D[D_SR] == 0)  // tg (4chi x cr) = t1 (4chi x rr) B_R (rr x cr)
-        g = {J.t1, D[D_RR], false, J.br, D[D_CR], false, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_RR]};
-      else               // tg = vdh' (4chi x r) V_R^H (r x cr)
-        g = {J.vdh, D[D_R], false, J.vr, nb, true, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_R]};
+      if (D[D_SR] == 0)  // tg (4chi x cr) = (vdh' S_R^-1) (U_R^H B_R)[:r, :]
+        set(J.vdh, D[D_R], false, J.pr, J.ldr, false, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_R]);
+      else               // tg = vdh' V_R[:, :r]^H
+        set(J.vdh, D[D_R], false, J.vr, nb, true, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_R]);
       return true;
     default:
       return false;
@@ -251,13 +275,54 @@ __global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm(const BondJob* jobs,
   if (!gemm_args(jobs[item], kind, sub, g)) return;
   if (g.m <= 0 || g.n <= 0) return;
   gemm_tile<double>(g.A, g.lda, g.ca, g.B, g.ldb, g.cb, g.C, g.ldc, g.m, g.n, g.k,
-                    mk<double>(1.0, 0.0), false, blockIdx.x, blockIdx.y, sm);
+                    mk<double>(g.alpha, 0.0), g.acc, blockIdx.x, blockIdx.y, sm);
+}
+
+// --------------------------------------------- singular values and rules
+// Truncation rule of Appendix A.2 on singular values s[0..n) given in
+// (eigenvalue) order: the smallest rank c whose discarded tail
+// sqrt(extra + sum_{i >= c} s_i^2) is strictly below eps * max(s); exact
+// zeros are never kept; rank >= 1; optional cap with the tie rule (a
+// multiplet split by the cap, neighbours within 1e-10 of the largest value,
+// is dropped whole).  Runs on one thread.
+__device__ inline int truncation_rank(const double* s, int n, double eps, double extra, int cap) {
+  double smax = 0.0;
+  int npos = 0;
+  for (int i = 0; i < n; ++i) {
+    smax = fmax(smax, s[i]);
+    if (s[i] > 0.0) npos = i + 1;
+  }
+  if (npos == 0) return 0;
+  const double thr = eps * smax;
+  int keep = npos;
+  double tail = extra;
+  for (int i = npos - 1; i >= 1; --i) {
+    tail += s[i] * s[i];
+    if (sqrt(tail) < thr) keep = i;
+    else break;
+  }
+  if (cap > 0 && keep > cap) {
+    keep = cap;
+    while (keep > 1 && fabs(s[keep - 1] - s[keep]) < 1e-10 * smax) --keep;
+  }
+  return max(keep, 1);
+}
+
+// Truncation ranks l, r from the (refined) singular values of B_L, B_R:
+// eps rule only.  One thread per item.
+__global__ void k_rule_b(const BondJob* jobs, int n_items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondJob& J = jobs[i];
+  int* D = J.dims;
+  D[D_L] = truncation_rank(J.sl, D[D_NL], J.eps, 0.0, 0);
+  D[D_R] = truncation_rank(J.sr, D[D_NR], J.eps, 0.0, 0);
 }
 
 // ------------------------------------------------------ X, Y (elementwise)
-// X (l x cl): side 0 -> S_L V_L^H; side 1 -> GEMM result already in x.  Both
-// then scaled by lam_n on the b index.  Y (rr x r): side 0 -> U_R S_R.
-// grid (blocks, items)
+// X (l x cl) times lam_n on the b index:  side 0: X[i,col] = s_i conj(V_L[col,i]);
+// side 1: X = (U_L^H B_L)[:l].  Y (rr x r): side 0: Y[row,j] = U_R[row,j] s_j;
+// side 1: Y = (B_R V_R)[:, :r].  grid (blocks, items)
 __global__ void k_form_xy(const ChainDev* chains, const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.y];
   const ChainDev& C = chains[J.chain];
@@ -270,20 +335,15 @@ __global__ void k_form_xy(const ChainDev* chains, const BondJob* jobs) {
        idx += (long long)gridDim.x * blockDim.x) {
     if (idx < nx) {
       const int i = (int)(idx / cl), col = (int)(idx - (long long)i * cl);
-      const double lb = lam_c[col % b];
       double2 v;
-      if (D[D_SL] == 0) {
-        const double s = sqrt(fmax(J.wl[i], 0.0));
-        v = cscale<double>(cconj<double>(J.vl[(long long)col * nb + i]), s);
-      } else {
-        v = J.x[idx];
-      }
-      J.x[idx] = cscale<double>(v, lb);
-    } else if (D[D_SR] == 0) {
+      if (D[D_SL] == 0) v = cscale<double>(cconj<double>(J.vl[(long long)col * nb + i]), J.sl[i]);
+      else v = J.pl[(long long)i * nb + col];
+      J.x[idx] = cscale<double>(v, lam_c[col % b]);
+    } else {
       const long long j = idx - nx;
       const int row = (int)(j / r), k = (int)(j - (long long)row * r);
-      const double s = sqrt(fmax(J.wr[k], 0.0));
-      J.y[j] = cscale<double>(J.vr[(long long)row * nb + k], s);
+      if (D[D_SR] == 0) J.y[j] = cscale<double>(J.vr[(long long)row * nb + k], J.sr[k]);
+      else J.y[j] = J.pr[(long long)row * J.ldr + k];
     }
   }
 }
@@ -301,7 +361,12 @@ __global__ void k_apply_gate(const BondJob* jobs) {
     D[D_N] = N;
     const int k = min(min(M, N), J.k_cap);
     D[D_K] = k;
-    D[D_GS] = k;
+    // M <= sketch cap: the identity is an orthonormal basis of the whole
+    // row space of D, so no range finder is needed (exact)
+    const int rf = (M > J.k_cap) ? 1 : 0;
+    D[D_RF] = rf;
+    D[D_GS] = rf ? k : 0;
+    if (!rf) D[D_KQ] = M;
   }
   __shared__ double2 g[256];
   __shared__ double red[4];
@@ -337,6 +402,16 @@ __global__ void k_apply_gate(const BondJob* jobs) {
 __global__ void k_sketch_init(const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.y];
   const int N = J.dims[D_N], K = J.dims[D_K];
+  if (J.dims[D_RF] == 0) {  // Q = identity (M x M) in ya
+    const int M = J.dims[D_M];
+    const long long tot = (long long)M * M;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+         idx += (long long)gridDim.x * blockDim.x) {
+      const int r = (int)(idx / M), c = (int)(idx - (long long)r * M);
+      J.ya[(long long)r * J.k_cap + c] = mk<double>(r == c ? 1.0 : 0.0, 0.0);
+    }
+    return;
+  }
   const long long tot = (long long)N * K;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -350,27 +425,52 @@ __global__ void k_sketch_init(const BondJob* jobs) {
 }
 
 // small dims bookkeeping kernel: dims[dst] = dims[src] for every item
-__global__ void k_copy_dim(const BondJob* jobs, int n_items, int dst, int src) {
+// (only where the range finder is active if only_rf)
+__global__ void k_copy_dim(const BondJob* jobs, int n_items, int dst, int src, int only_rf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_items) jobs[i].dims[dst] = jobs[i].dims[src];
+  if (i < n_items && (!only_rf || jobs[i].dims[D_RF])) jobs[i].dims[dst] = jobs[i].dims[src];
 }
 
-// ||Q^H D||_F^2 -> norms[1]; extra tail = max(||D||^2 - ||Q^H D||^2, 0) -> norms[2]
-__global__ void k_rr_norms(const BondJob* jobs) {
+// p = D (copy) when the sketch does not span D's whole range; the residual
+// D - Q Q^H D is then formed by GK_RESID.  grid (blocks, items)
+__global__ void k_resid_copy(const BondJob* jobs) {
+  const BondJob& J = jobs[blockIdx.y];
+  const int* D = J.dims;
+  const int M = D[D_M], N = D[D_N];
+  if (D[D_K] >= min(M, N)) return;
+  const long long tot = (long long)M * N;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x)
+    J.p[idx] = J.d[idx];
+}
+
+// extra tail = ||D - Q Q^H D||_F^2 (0 when the sketch spans the range)
+// -> norms[2].  One block per item.
+__global__ void k_resid_norm(const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.x];
-  const int kq = J.dims[D_KQ], N = J.dims[D_N];
+  const int* D = J.dims;
+  const int M = D[D_M], N = D[D_N];
   __shared__ double red[4];
   double part = 0.0;
-  for (long long idx = threadIdx.x; idx < (long long)kq * N; idx += blockDim.x) part += cabs2<double>(J.bm[idx]);
+  if (D[D_K] < min(M, N))
+    for (long long idx = threadIdx.x; idx < (long long)M * N; idx += blockDim.x) part += cabs2<double>(J.p[idx]);
   const double tot = block_sum(part, red);
-  if (threadIdx.x == 0) {
-    J.norms[1] = tot;
-    J.norms[2] = fmax(J.norms[0] - tot, 0.0);
-  }
+  if (threadIdx.x == 0) J.norms[2] = tot;
 }
 
-// rows of vdh /= sigma_i (V^D^H = S^-1 W^H B); side-0 scalings used by the
-// rebuilds: ud rows (l,s') /= sigma_L[l], vdh' columns r /= sigma_R[r].
+// New bond dimension from the (refined) singular values of D: eps rule with
+// the energy outside the sketch as extra tail, chi_max cap, tie rule.
+// One thread per item.
+__global__ void k_rule_d(const BondJob* jobs, int n_items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondJob& J = jobs[i];
+  int* D = J.dims;
+  D[D_CHI] = truncation_rank(J.sk, D[D_KQ], J.eps, J.norms[2], J.chi_max);
+}
+
+// vdh rows /= s_i (V^D^H = S^-1 W^H B); side-0 scalings used by the
+// rebuilds: ud rows (l,s') /= s_L[l], vdh' columns r /= s_R[r].
 __global__ void k_scale_factors(const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.y];
   const int* D = J.dims;
@@ -380,13 +480,13 @@ __global__ void k_scale_factors(const BondJob* jobs) {
        idx += (long long)gridDim.x * blockDim.x) {
     if (idx < nv) {
       const int i = (int)(idx / N), col = (int)(idx - (long long)i * N);
-      double f = 1.0 / sqrt(fmax(J.wk[i], 1e-300));
-      if (D[D_SR] == 0) f /= sqrt(fmax(J.wr[col % r], 1e-300));
+      double f = 1.0 / fmax(J.sk[i], 1e-300);
+      if (D[D_SR] == 0) f /= fmax(J.sr[col % r], 1e-300);
       J.vdh[idx] = cscale<double>(J.vdh[idx], f);
     } else if (D[D_SL] == 0) {
       const long long j = idx - nv;
       const int row = (int)(j / chi);
-      J.ud[j] = cscale<double>(J.ud[j], 1.0 / sqrt(fmax(J.wl[row / 4], 1e-300)));
+      J.ud[j] = cscale<double>(J.ud[j], 1.0 / fmax(J.sl[row / 4], 1e-300));
     }
   }
 }
@@ -407,7 +507,6 @@ __global__ void k_store_gamma(const ChainDev* chains, const BondJob* jobs, int s
     const long long tot = (long long)a * e * 4 * chi;
     for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
          idx += (long long)gridDim.x * blockDim.x) {
-      // idx over output layout [a][s][e][b']
       const int bp = (int)(idx % chi);
       long long rest = idx / chi;
       const int ei = (int)(rest % e);
@@ -436,11 +535,10 @@ __global__ void k_finalize(const ChainDev* chains, const BondJob* jobs) {
   const int chi = J.dims[D_CHI];
   __shared__ double red[4];
   double part = 0.0;
-  for (int i = threadIdx.x; i < chi; i += blockDim.x) part += fmax(J.wk[i], 0.0);
-  const double nrm2 = block_sum(part, red);
-  const double nrm = sqrt(nrm2);
+  for (int i = threadIdx.x; i < chi; i += blockDim.x) part += J.sk[i] * J.sk[i];
+  const double nrm = sqrt(block_sum(part, red));
   double* lam = C.lam + (long long)(J.bond + 1) * C.chi_cap;
-  for (int i = threadIdx.x; i < chi; i += blockDim.x) lam[i] = sqrt(fmax(J.wk[i], 0.0)) / nrm;
+  for (int i = threadIdx.x; i < chi; i += blockDim.x) lam[i] = J.sk[i] / nrm;
   if (threadIdx.x == 0) {
     const int* D = J.dims;
     int bad = 0;
@@ -448,11 +546,17 @@ __global__ void k_finalize(const ChainDev* chains, const BondJob* jobs) {
     if (!isfinite(nrm) || !isfinite(J.norms[0])) bad |= ST_NONFINITE;
     if (chi < 1 || D[D_L] < 1 || D[D_R] < 1) bad |= ST_ZERO;
     if (bad) atomicOr(C.status, bad);
-    else atomicAdd(C.log_scale, log(nrm));
+    J.norms[3] = bad ? 0.0 : log(nrm);   // summed in item order by k_logscale
     C.chi[J.bond + 1] = chi;
     C.parity[J.bond] ^= 1;
     C.parity[J.bond + 1] ^= 1;
   }
+}
+
+// log-scale += log ||S^D|| of every item, in item order (deterministic).
+__global__ void k_logscale(const ChainDev* chains, const BondJob* jobs, int n_items) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < n_items; ++i) *chains[jobs[i].chain].log_scale += jobs[i].norms[3];
 }
 
 }  // namespace ptt

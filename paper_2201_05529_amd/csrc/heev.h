@@ -11,10 +11,25 @@
 //           shifted tridiagonal), re-orthogonalised within clusters of
 //           (near-)degenerate eigenvalues
 //  stage 5  (separate kernel) back-transformation V = Q Z with the stored
-//           reflectors, optionally scaling column k
+//           reflectors
+//  stage 6  (separate kernels) two passes of block classical Gram-Schmidt
+//           of the columns of V in eigenvalue order, then the optional
+//           column scaling
+//
+// Inverse iteration leaves eigenvectors whose mutual overlaps are about
+// eps |lambda_0| / gap.  In a Gram matrix with a fast-decaying spectrum most
+// gaps are tiny next to |lambda_0|, so overlaps of 1e-7 are common; the
+// truncated SVDs built on these vectors reconstruct the two-site block only
+// to that level.  Stage 6 removes the overlaps: one pass maps V to
+// V (I - U), U the strictly upper part of V^H V, and renormalises the
+// columns, which leaves overlaps of second order; the second pass brings
+// them to rounding level.  Each column only loses components along the
+// columns of larger eigenvalues, so the eigen-residuals stay at rounding
+// level as well.
 #pragma once
 
 #include "device_common.h"
+#include "gemm.h"
 
 namespace ptt {
 
@@ -22,7 +37,8 @@ enum HeevRule : int {
   RULE_ALL = 0,    // every eigenpair with a positive eigenvalue
   RULE_EPS = 1,    // sqrt(eigenvalues) as singular values: eps rule only
   RULE_CAP = 2,    // eps rule + extra tail + chi_max cap + tie rule
-  RULE_RANK = 3    // numerical rank: lambda_k > rank_tol * lambda_0
+  RULE_RANK = 3,   // numerical rank: lambda_k > rank_tol * lambda_0
+  RULE_FULL = 4    // every eigenpair (the caller applies its own rule)
 };
 
 enum HeevScale : int { SCALE_NONE = 0, SCALE_INV_SQRT = 1, SCALE_SQRT = 2 };
@@ -62,10 +78,7 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob*
   __shared__ double2 s_tau;
   __shared__ double s_beta;
   __shared__ int s_nvec;
-  if (n <= 0) {
-    if (tid == 0) *J.nvec_out = 0;
-    return;
-  }
+  if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
   double2* A = J.a;
   const int lda = J.lda;
   double* dd = J.tri;              // diagonal of T
@@ -188,7 +201,9 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob*
     const double* w = J.w;
     int nvec = 0;
     const double lam0 = w[0];
-    if (J.rule == RULE_RANK) {
+    if (J.rule == RULE_FULL) {
+      nvec = n;
+    } else if (J.rule == RULE_RANK) {
       while (nvec < n && w[nvec] > J.rank_tol * lam0 && w[nvec] > 0.0) ++nvec;
     } else {
       int npos = 0;
@@ -290,10 +305,16 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob*
   // member against its predecessors and iterate again (wave 0)
   if (tid < 64) {
     const int lane = tid;
+    // clusters are formed among well-determined eigenvalues only
+    // (lambda > 1e-12 |lambda_0|); below that the eigenvectors of a Gram
+    // matrix are not resolved in double precision anyway
     const double gap_tol = 1e-10 * fmax(fabs(J.w[0]), 1e-300);
+    const double floor_val = 1e-12 * fabs(J.w[0]);
+    int nclu = 0;
+    while (nclu < nvec && J.w[nclu] > floor_val) ++nclu;
     int start = 0;
-    for (int k = 1; k <= nvec; ++k) {
-      const bool brk = (k == nvec) || (fabs(J.w[k - 1] - J.w[k]) > gap_tol);
+    for (int k = 1; k <= nclu; ++k) {
+      const bool brk = (k == nclu) || (fabs(J.w[k - 1] - J.w[k]) > gap_tol);
       if (!brk) continue;
       for (int j = start + 1; j < k; ++j) {
         for (int pass = 0; pass < 2; ++pass) {
@@ -336,6 +357,54 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob*
         }
       }
       start = k;
+    }
+  }
+  __syncthreads();
+  // vectors of eigenvalues below the resolution floor (and any later ones)
+  // are undetermined individually; orthonormalise them against every
+  // earlier vector (modified Gram-Schmidt, two passes, whole workgroup) so
+  // the eigenvector matrix is unitary -- any orthonormal basis of that
+  // subspace is equally valid.
+  {
+    __shared__ double dots[1024];
+    __shared__ int s_j0;
+    if (tid == 0) {
+      const double floor_val = 1e-10 * fabs(J.w[0]);
+      int j0 = 0;
+      while (j0 < nvec && J.w[j0] > floor_val) ++j0;
+      s_j0 = j0;
+    }
+    __syncthreads();
+    for (int j = max(s_j0, 1); j < nvec; ++j) {
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int i = tid; i < j; i += HEEV_THREADS) {
+            double acc = 0.0;
+            for (int r = 0; r < n; ++r) acc += W(5, r, i) * W(5, r, j);
+            dots[i] = acc;
+          }
+          __syncthreads();
+          for (int r = tid; r < n; r += HEEV_THREADS) {
+            double acc = W(5, r, j);
+            for (int i = 0; i < j; ++i) acc -= dots[i] * W(5, r, i);
+            W(5, r, j) = acc;
+          }
+          __syncthreads();
+        }
+        double part = 0.0;
+        for (int r = tid; r < n; r += HEEV_THREADS) part += W(5, r, j) * W(5, r, j);
+        const double nrm = sqrt(block_sum(part, red));
+        if (nrm > 1e-8 || attempt == 1) {
+          const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+          for (int r = tid; r < n; r += HEEV_THREADS) W(5, r, j) *= inv;
+          __syncthreads();
+          break;
+        }
+        // nearly parallel to the earlier vectors: restart from a fresh vector
+        for (int r = tid; r < n; r += HEEV_THREADS)
+          W(5, r, j) = u01(splitmix64(0xC2B2AE3D27D4EB4Full * (j + 1) + r)) - 0.5;
+        __syncthreads();
+      }
     }
   }
   __syncthreads();
@@ -411,15 +480,73 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_backtransform_kernel(const 
   }
   for (int e = tid; e < n * ncol; e += HEEV_THREADS) {
     const int i = e / ncol, c = e - i * ncol;
-    double2 val = zs[i * HEEV_BT_COLS + c];
-    const int k = c0 + c;
-    if (J.scale != SCALE_NONE) {
-      const double lam = fmax(J.w[k], 1e-300);
-      const double f = (J.scale == SCALE_INV_SQRT) ? 1.0 / sqrt(lam) : sqrt(lam);
-      val = cscale<double>(val, f);
-    }
-    J.v[(size_t)i * J.ldv + k] = val;
+    J.v[(size_t)i * J.ldv + c0 + c] = zs[i * HEEV_BT_COLS + c];
   }
+}
+
+// --------------------------------------------------------------- stage 6
+// Scratch in the (by now free) inverse-iteration workspace, viewed as
+// complex: G = V^H V at [0, n_cap^2), T = V (I - U) at [n_cap^2, 2 n_cap^2),
+// both with leading dimension n_cap.
+__device__ inline double2* orth_g(const HeevJob& J) { return reinterpret_cast<double2*>(J.work); }
+__device__ inline double2* orth_t(const HeevJob& J) {
+  return reinterpret_cast<double2*>(J.work) + (size_t)J.n_cap * J.n_cap;
+}
+
+// kind 0: G = V^H V (nvec x nvec);  kind 1: T = V M (n x nvec), M = I - U.
+// grid (tiles_m, tiles_n, jobs)
+__global__ void __launch_bounds__(GEMM_THREADS) heev_orth_gemm(const HeevJob* jobs, int kind) {
+  __shared__ GemmSmem<double> sm;
+  const HeevJob& J = jobs[blockIdx.z];
+  const int n = *J.n_ptr;
+  if (n <= 0) return;
+  const int nvec = *J.nvec_out;
+  if (nvec < 2) return;
+  if (kind == 0)
+    gemm_tile<double>(J.v, J.ldv, true, J.v, J.ldv, false, orth_g(J), J.n_cap, nvec, nvec, n,
+                      mk<double>(1.0, 0.0), false, blockIdx.x, blockIdx.y, sm);
+  else
+    gemm_tile<double>(J.v, J.ldv, false, orth_g(J), J.n_cap, false, orth_t(J), J.n_cap, n, nvec, nvec,
+                      mk<double>(1.0, 0.0), false, blockIdx.x, blockIdx.y, sm);
+}
+
+// G <- I - strictly_upper(G).  grid (blocks, jobs)
+__global__ void heev_orth_mfix(const HeevJob* jobs) {
+  const HeevJob& J = jobs[blockIdx.y];
+  const int n = *J.n_ptr;
+  if (n <= 0) return;
+  const int nvec = *J.nvec_out;
+  if (nvec < 2) return;
+  double2* G = orth_g(J);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)nvec * nvec;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / nvec), j = (int)(e - (long long)i * nvec);
+    double2& g = G[(size_t)i * J.n_cap + j];
+    g = (i < j) ? mk<double>(-g.x, -g.y) : mk<double>(i == j ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// V <- T with unit columns (from_t), or V's own columns renormalised; the
+// last call also applies the column scaling.  One thread per column.
+// grid (ceil(n_cap / 256), jobs)
+__global__ void heev_orth_norm(const HeevJob* jobs, int from_t, int final_pass) {
+  const HeevJob& J = jobs[blockIdx.y];
+  const int n = *J.n_ptr;
+  if (n <= 0) return;
+  const int nvec = *J.nvec_out;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nvec) return;
+  const bool use_t = from_t && nvec >= 2;
+  const double2* src = use_t ? orth_t(J) : J.v;
+  const int lds = use_t ? J.n_cap : J.ldv;
+  double acc = 0.0;
+  for (int r = 0; r < n; ++r) acc += cabs2<double>(src[(size_t)r * lds + k]);
+  double f = acc > 0.0 ? 1.0 / sqrt(acc) : 0.0;
+  if (final_pass && J.scale != SCALE_NONE) {
+    const double lam = fmax(J.w[k], 1e-300);
+    f *= (J.scale == SCALE_INV_SQRT) ? 1.0 / sqrt(lam) : sqrt(lam);
+  }
+  for (int r = 0; r < n; ++r) J.v[(size_t)r * J.ldv + k] = cscale<double>(src[(size_t)r * lds + k], f);
 }
 
 }  // namespace ptt

@@ -46,6 +46,10 @@ struct Sublayer {
   HeevJob* heev_oy = nullptr;    // device [n]
   HeevJob* heev_oz = nullptr;    // device [n]
   HeevJob* heev_rr = nullptr;    // device [n]
+  ptt::RefineJob* ref_b = nullptr;  // device [2 n]: B_L, B_R
+  ptt::RefineJob* ref_d = nullptr;  // device [n]
+  HeevJob* heev_ref_b = nullptr;    // device [2 n]
+  HeevJob* heev_ref_d = nullptr;    // device [n]
   std::vector<BondJob> host_jobs;
 };
 
@@ -66,6 +70,8 @@ struct pt_tebd {
   unsigned long long seed = 0;
   int power_iters = 1;
   int oversample = 64;
+  int refine_levels = 3;
+  double refine_tau = 1e-4;
   int pt_steps = 0;           // shortest PT-MPO length
   Caps cap{};
   hipStream_t stream = nullptr;
@@ -136,7 +142,9 @@ struct DevPtrs {
   std::vector<double2*> h_refl[2];
   std::vector<double*> h_tri[2], h_work[2], h_z[2];
   BondJob* jobs[2];
-  HeevJob *hb[2], *hoy[2], *hoz[2], *hrr[2];
+  HeevJob *hb[2], *hoy[2], *hoz[2], *hrr[2], *hrb[2], *hrd[2];
+  ptt::RefineJob *rb[2], *rd[2];
+  std::vector<int*> blk;   // per slot: 3 x [2]
 };
 
 // Walk the workspace layout once with a null base (sizes only) or with the
@@ -197,6 +205,16 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     J.p = bp.take<double2>(dn * dn);
     J.d = bp.take<double2>(dn * dn);
     J.wk = bp.take<double>(nh);
+    J.sl = bp.take<double>(nh);
+    J.sr = bp.take<double>(nh);
+    J.sk = bp.take<double>(nh);
+    J.pl = bp.take<double2>(std::max(rl, nb) * nb);
+    J.pr = bp.take<double2>(nb * std::max(rl, nb));
+    J.tpl = bp.take<double2>(std::max(rl, nb) * nb);
+    J.tvl = bp.take<double2>(nb * nb);
+    J.tpr = bp.take<double2>(nb * std::max(rl, nb));
+    J.tvr = bp.take<double2>(nb * nb);
+    P.blk.push_back(bp.take<int>(6));
     J.omega = bp.take<double2>(dn * kc);
     J.ya = bp.take<double2>(dn * kc);
     J.yb = bp.take<double2>(dn * kc);
@@ -206,8 +224,8 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     J.vk = bp.take<double2>(kc * kc);
     J.bm = bp.take<double2>(kc * dn);
     J.ud = bp.take<double2>(dn * c.chi_cap);
-    J.vdh = bp.take<double2>((size_t)c.chi_cap * dn);
-    J.t1 = bp.take<double2>(4 * (size_t)c.chi_cap * nb);
+    J.vdh = bp.take<double2>(kc * dn);
+    J.t1 = nullptr;
     J.tg = bp.take<double2>(4 * (size_t)c.chi_cap * rl);
     P.slots.push_back(J);
     for (int set = 0; set < 2; ++set) {
@@ -224,6 +242,10 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     P.hoy[par] = bp.take<HeevJob>(n);
     P.hoz[par] = bp.take<HeevJob>(n);
     P.hrr[par] = bp.take<HeevJob>(n);
+    P.hrb[par] = bp.take<HeevJob>(2 * n);
+    P.hrd[par] = bp.take<HeevJob>(n);
+    P.rb[par] = bp.take<ptt::RefineJob>(2 * n);
+    P.rd[par] = bp.take<ptt::RefineJob>(n);
   }
   if (out) *out = P;
   return bp.off + 256;
@@ -321,11 +343,43 @@ void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int
   ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs);
 }
 
+int elem_blocks(long long n);
+
 void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
   ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_THREADS, 0, st>>>(jobs);
   dim3 grid((n_cap + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, n_jobs);
   const size_t shm = (size_t)n_cap * ptt::HEEV_BT_COLS * sizeof(double2);
   ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, shm, st>>>(jobs);
+  const int tiles = (n_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM;
+  const dim3 gg(tiles, tiles, n_jobs);
+  const dim3 gn((n_cap + 255) / 256, n_jobs);
+  for (int pass = 0; pass < 2; ++pass) {
+    ptt::heev_orth_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs, 0);
+    ptt::heev_orth_mfix<<<dim3(elem_blocks((long long)n_cap * n_cap), n_jobs), kThreads, 0, st>>>(jobs);
+    ptt::heev_orth_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs, 1);
+    ptt::heev_orth_norm<<<gn, 256, 0, st>>>(jobs, 1, pass == 1);
+  }
+}
+
+int elem_blocks(long long n);
+
+// levels of block refinement of Gram-based singular values (refine.h)
+void run_refine(pt_tebd* h, const ptt::RefineJob* R, const HeevJob* H, int n_jobs, int m_cap, int n_cap,
+                int nh) {
+  hipStream_t st = h->stream;
+  ptt::k_ref_norms<<<n_jobs, kThreads, 0, st>>>(R);
+  for (int level = 0; level < h->refine_levels; ++level) {
+    ptt::k_ref_select<<<(n_jobs + 63) / 64, 64, 0, st>>>(R, n_jobs, h->refine_tau, level);
+    dim3 gg((nh + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (nh + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
+    ptt::k_ref_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(R, ptt::RK_GRAM);
+    launch_heev(st, H, n_jobs, nh);
+    dim3 gp((m_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (n_cap + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
+    ptt::k_ref_gemm<<<gp, ptt::GEMM_THREADS, 0, st>>>(R, ptt::RK_ROTP);
+    dim3 gv((nh + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (nh + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
+    ptt::k_ref_gemm<<<gv, ptt::GEMM_THREADS, 0, st>>>(R, ptt::RK_ROTV);
+    ptt::k_ref_copy<<<dim3(elem_blocks((long long)m_cap * n_cap), n_jobs), kThreads, 0, st>>>(R);
+    ptt::k_ref_norms<<<n_jobs, kThreads, 0, st>>>(R);
+  }
 }
 
 int elem_blocks(long long n) { return (int)std::min<long long>(std::max<long long>((n + kThreads - 1) / kThreads, 1), 1024); }
@@ -336,18 +390,23 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   const Caps& c = h->cap;
   hipStream_t st = h->stream;
   const long long rl = (long long)c.chi_cap * c.xi_cap;
+  const int wide = (int)std::max<long long>(rl, c.nb);
   const BondJob* J = S.jobs;
-  const int eb = elem_blocks(2 * rl * c.nb);
-  ptt::k_pack<<<dim3(eb, n), kThreads, 0, st>>>(chains, J);
+  // (c)-(e): B_L, B_R, their Gram matrices, eigenpairs, singular values, ranks
+  ptt::k_pack<<<dim3(elem_blocks(2 * rl * c.nb), n), kThreads, 0, st>>>(chains, J);
   launch_gemm(st, J, n, ptt::GK_GRAM_B, 2, c.nb, c.nb);
   launch_heev(st, S.heev_b, 2 * n, c.nh);
-  launch_gemm(st, J, n, ptt::GK_XY, 2, c.nb, c.nb);
+  launch_gemm(st, J, n, ptt::GK_PROD_B, 2, wide, wide);
+  run_refine(h, S.ref_b, S.heev_ref_b, 2 * n, wide, wide, c.nb);
+  ptt::k_rule_b<<<(n + 63) / 64, 64, 0, st>>>(J, n);
   ptt::k_form_xy<<<dim3(elem_blocks(2LL * c.nb * c.nb), n), kThreads, 0, st>>>(chains, J);
+  // (e)-(f): D
   launch_gemm(st, J, n, ptt::GK_P, 1, c.dn, c.dn);
   ptt::k_apply_gate<<<dim3(elem_blocks((long long)c.nb * c.nb), n), kThreads, 0, st>>>(J);
+  // (f)-(g): leading singular subspace of D
   ptt::k_sketch_init<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J);
   launch_gemm(st, J, n, ptt::GK_SKETCH, 1, c.dn, c.kc);
-  auto copy_dim = [&](int dst, int src) { ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, dst, src); };
+  auto copy_dim = [&](int dst, int src) { ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, dst, src, 1); };
   auto orth_y = [&]() {
     launch_gemm(st, J, n, ptt::GK_GRAM_YA, 1, c.kc, c.kc);
     launch_heev(st, S.heev_oy, n, c.kc);
@@ -373,20 +432,24 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     orth_y();
   }
   launch_gemm(st, J, n, ptt::GK_QH_D, 1, c.kc, c.dn);
-  ptt::k_rr_norms<<<n, kThreads, 0, st>>>(J);
-  copy_dim(ptt::D_GS, ptt::D_KQ);
+  ptt::k_resid_copy<<<dim3(elem_blocks((long long)c.dn * c.dn), n), kThreads, 0, st>>>(J);
+  launch_gemm(st, J, n, ptt::GK_RESID, 1, c.dn, c.dn);
+  ptt::k_resid_norm<<<n, kThreads, 0, st>>>(J);
+  ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, ptt::D_GS, ptt::D_KQ, 0);
   launch_gemm(st, J, n, ptt::GK_GRAM_BM, 1, c.kc, c.kc);
   launch_heev(st, S.heev_rr, n, c.kc);
+  launch_gemm(st, J, n, ptt::GK_C, 1, c.kc, c.dn);
+  run_refine(h, S.ref_d, S.heev_ref_d, n, c.kc, c.dn, c.kc);
+  ptt::k_rule_d<<<(n + 63) / 64, 64, 0, st>>>(J, n);
   launch_gemm(st, J, n, ptt::GK_UD, 1, c.dn, c.chi_cap);
-  launch_gemm(st, J, n, ptt::GK_VDH, 1, c.chi_cap, c.dn);
   ptt::k_scale_factors<<<dim3(elem_blocks(2LL * c.dn * c.chi_cap), n), kThreads, 0, st>>>(J);
-  launch_gemm(st, J, n, ptt::GK_T1, 1, c.nb, 4 * c.chi_cap);
+  // (g)-(h): new site tensors
   launch_gemm(st, J, n, ptt::GK_NEWL, 1, (int)rl, 4 * c.chi_cap);
   ptt::k_store_gamma<<<dim3(elem_blocks(rl * 4 * c.chi_cap), n), kThreads, 0, st>>>(chains, J, 0);
-  launch_gemm(st, J, n, ptt::GK_T2, 1, 4 * c.chi_cap, c.nb);
   launch_gemm(st, J, n, ptt::GK_NEWR, 1, 4 * c.chi_cap, (int)rl);
   ptt::k_store_gamma<<<dim3(elem_blocks(rl * 4 * c.chi_cap), n), kThreads, 0, st>>>(chains, J, 1);
   ptt::k_finalize<<<n, kThreads, 0, st>>>(chains, J);
+  ptt::k_logscale<<<1, 64, 0, st>>>(chains, J, n);
 }
 
 void run_half_step(pt_tebd* h, const ChainDev* chains, ChainDev* host_view, double2* /*unused*/) {
@@ -501,6 +564,7 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
   auto h = std::make_unique<pt_tebd>();
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
+  h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", 3));
   h->cap = compute_caps(cfg, h->oversample);
   const Caps& c = h->cap;
   const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
@@ -642,7 +706,13 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
     S.heev_oy = P.hoy[par];
     S.heev_oz = P.hoz[par];
     S.heev_rr = P.hrr[par];
+    S.ref_b = P.rb[par];
+    S.ref_d = P.rd[par];
+    S.heev_ref_b = P.hrb[par];
+    S.heev_ref_d = P.hrd[par];
     std::vector<HeevJob> hb2(2 * std::max(n, 1)), hoy(std::max(n, 1)), hoz(std::max(n, 1)), hrr(std::max(n, 1));
+    std::vector<HeevJob> hrb(2 * std::max(n, 1)), hrd(std::max(n, 1));
+    std::vector<ptt::RefineJob> rb(2 * std::max(n, 1)), rd(std::max(n, 1));
     for (int i = 0; i < n; ++i) {
       BondJob J = P.slots[i];
       J.chain = 0;
@@ -654,13 +724,14 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
       J.seed = ptt::splitmix64(cfg->seed ^ (0xA24BAED4963EE407ull * (unsigned long long)(J.bond + 1)));
       J.nb_cap = c.nb;
       J.dn_cap = c.dn;
+      J.ldr = std::max(c.chi_cap * c.xi_cap, c.nb);
       S.host_jobs.push_back(J);
       int* st0 = P.status[0];
       fill_heev(hb2[2 * i], J.gl, c.nb, J.dims + ptt::D_NL, J.wl, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
-                P.h_z[0][i], c.nh, J.dims + ptt::D_L, ptt::RULE_EPS, J.eps, 0, nullptr, 0.0, J.vl, c.nb,
+                P.h_z[0][i], c.nh, J.dims + ptt::D_L, ptt::RULE_FULL, J.eps, 0, nullptr, 0.0, J.vl, c.nb,
                 ptt::SCALE_NONE, st0);
       fill_heev(hb2[2 * i + 1], J.gr, c.nb, J.dims + ptt::D_NR, J.wr, P.h_refl[1][i], P.h_tri[1][i], P.h_work[1][i],
-                P.h_z[1][i], c.nh, J.dims + ptt::D_R, ptt::RULE_EPS, J.eps, 0, nullptr, 0.0, J.vr, c.nb,
+                P.h_z[1][i], c.nh, J.dims + ptt::D_R, ptt::RULE_FULL, J.eps, 0, nullptr, 0.0, J.vr, c.nb,
                 ptt::SCALE_NONE, st0);
       fill_heev(hoy[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
                 P.h_z[0][i], c.nh, J.dims + ptt::D_KQ, ptt::RULE_RANK, 0.0, 0, nullptr, 1e-15, J.vk, c.kc,
@@ -668,8 +739,37 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
       hoz[i] = hoy[i];
       hoz[i].nvec_out = J.dims + ptt::D_KZ;
       fill_heev(hrr[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
-                P.h_z[0][i], c.nh, J.dims + ptt::D_CHI, ptt::RULE_CAP, J.eps, cfg->chi_max, J.norms + 2, 0.0,
+                P.h_z[0][i], c.nh, J.dims + ptt::D_CHI, ptt::RULE_FULL, J.eps, cfg->chi_max, J.norms + 2, 0.0,
                 J.vk, c.kc, ptt::SCALE_NONE, st0);
+      int* blk = P.blk[i];
+      // B_L: columns of pl (rl x n) on side 0, rows of pl (n x cl) on side 1
+      ptt::RefineJob& RL = rb[2 * i];
+      RL = ptt::RefineJob{};
+      RL.P = J.pl; RL.ldp = c.nb; RL.ldp_ptr = nullptr; RL.cols = 0; RL.side_ptr = J.dims + ptt::D_SL; RL.side_cols = 0;
+      RL.len_cols = J.dims + ptt::D_RL; RL.len_rows = J.dims + ptt::D_CL; RL.n_ptr = J.dims + ptt::D_NL;
+      RL.V = J.vl; RL.ldv = c.nb; RL.nv_ptr = J.dims + ptt::D_NL; RL.s = J.sl; RL.blk = blk;
+      RL.G = J.gl; RL.ldg = c.nb; RL.W = J.x; RL.ldw = c.nb; RL.TP = J.tpl; RL.ldtp = c.nb; RL.TV = J.tvl; RL.ldtv = c.nb;
+      // B_R: rows of pr (n x cr) on side 0, columns of pr (rr x n) on side 1
+      ptt::RefineJob& RR = rb[2 * i + 1];
+      RR = ptt::RefineJob{};
+      RR.P = J.pr; RR.ldp = J.ldr; RR.ldp_ptr = nullptr; RR.cols = 0; RR.side_ptr = J.dims + ptt::D_SR; RR.side_cols = 1;
+      RR.len_cols = J.dims + ptt::D_RR; RR.len_rows = J.dims + ptt::D_CR; RR.n_ptr = J.dims + ptt::D_NR;
+      RR.V = J.vr; RR.ldv = c.nb; RR.nv_ptr = J.dims + ptt::D_NR; RR.s = J.sr; RR.blk = blk + 2;
+      RR.G = J.gr; RR.ldg = c.nb; RR.W = J.y; RR.ldw = c.nb; RR.TP = J.tpr; RR.ldtp = J.ldr; RR.TV = J.tvr; RR.ldtv = c.nb;
+      // D: rows of vdh = W^H Q^H D (KQ x N, leading dim N)
+      ptt::RefineJob& RD = rd[i];
+      RD = ptt::RefineJob{};
+      RD.P = J.vdh; RD.ldp = 0; RD.ldp_ptr = J.dims + ptt::D_N; RD.cols = 0; RD.side_ptr = nullptr;
+      RD.len_cols = J.dims + ptt::D_N; RD.len_rows = J.dims + ptt::D_N; RD.n_ptr = J.dims + ptt::D_KQ;
+      RD.V = J.vk; RD.ldv = c.kc; RD.nv_ptr = J.dims + ptt::D_KQ; RD.s = J.sk; RD.blk = blk + 4;
+      RD.G = J.gk; RD.ldg = c.kc; RD.W = J.omega; RD.ldw = c.kc; RD.TP = J.za; RD.ldtp = c.dn; RD.TV = J.zb; RD.ldtv = c.kc;
+      fill_heev(hrb[2 * i], J.gl, c.nb, blk + 1, J.wl, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i], P.h_z[0][i],
+                c.nh, J.dims + ptt::D_L, ptt::RULE_FULL, 0.0, 0, nullptr, 0.0, J.x, c.nb, ptt::SCALE_NONE, st0);
+      fill_heev(hrb[2 * i + 1], J.gr, c.nb, blk + 3, J.wr, P.h_refl[1][i], P.h_tri[1][i], P.h_work[1][i],
+                P.h_z[1][i], c.nh, J.dims + ptt::D_R, ptt::RULE_FULL, 0.0, 0, nullptr, 0.0, J.y, c.nb,
+                ptt::SCALE_NONE, st0);
+      fill_heev(hrd[i], J.gk, c.kc, blk + 5, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i], P.h_z[0][i],
+                c.nh, J.dims + ptt::D_CHI, ptt::RULE_FULL, 0.0, 0, nullptr, 0.0, J.omega, c.kc, ptt::SCALE_NONE, st0);
     }
     if (n > 0) {
       bool ok = check(hipMemcpyAsync(S.jobs, S.host_jobs.data(), n * sizeof(BondJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
@@ -677,6 +777,10 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
                 check(hipMemcpyAsync(S.heev_oy, hoy.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_oz, hoz.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_rr, hrr.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_ref_b, hrb.data(), 2 * n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_ref_d, hrd.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.ref_b, rb.data(), 2 * n * sizeof(ptt::RefineJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.ref_d, rd.data(), n * sizeof(ptt::RefineJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipStreamSynchronize(st), hp, "jobs sync");
       if (!ok) return PT_TEBD_EDEVICE;
     }
@@ -1004,7 +1108,8 @@ extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule,
   pt_tebd_status st = PT_TEBD_OK;
   if (ok) {
     HeevJob J{};
-    const int r = rule == 0 ? ptt::RULE_ALL : rule == 1 ? ptt::RULE_EPS : rule == 2 ? ptt::RULE_CAP : ptt::RULE_RANK;
+    const int r = rule == 0 ? ptt::RULE_ALL : rule == 1 ? ptt::RULE_EPS : rule == 2 ? ptt::RULE_CAP
+                : rule == 3 ? ptt::RULE_RANK : ptt::RULE_FULL;
     fill_heev(J, da, n, dn, dw, drefl, dtri, dwork, dz, n, dnvec, r, eps, cap, dextra, eps, dv, n, ptt::SCALE_NONE, dstat);
     const double zero = 0.0;
     const int zi = 0;

@@ -133,5 +133,5 @@ def random_small_chain(seed, n_sites, n_steps=4, with_bath_sites=(0,), k_cut=3,
     baths = [bath(s, rng.uniform(0.05, 0.3), 4.0, rng.uniform(0.5, 2.0), k_cut)
              for s in with_bath_sites]
     return make_chain(f"small{seed}", n_sites, bonds, fields, rho0, dt=dt, n_steps=n_steps,
-                      baths=baths, chi_max=chi_max if chi_max else 1 << 20,
+                      baths=baths, chi_max=chi_max if chi_max else 256,
                       xi_max=xi_max if xi_max else 4 ** max(k_cut, 1), eps=eps, eps_tempo=eps)
