@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the PT-TEBD hot path on one GPU.
+
+One step = one full time step Delta t of the chain (Sec. II, the step of
+eq. propagator-env: two chain half-steps of three Trotter sublayers of
+two-site updates, and the absorption of every bath's PT-MPO tensor in
+between) followed by one read-out of <sigma^z_n> on every site.  A
+site-update is one site advanced by one Delta t, so a run of K steps of an
+N-site chain counts N*K site-updates.
+
+Default workload: the N = 21 XY chain with a bath on every site (chi <= 64,
+xi <= 24, dt = 0.1, 100 steps).  The timed region runs the workload's steps
+1..K from the initial state on a fresh handle, inputs and PT-MPOs already
+resident in device memory; gate build and PT-MPO build/upload are timed
+separately and excluded.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "site-updates/s, XY N=21 chi=64, FP32-mixed vs FP64 at <=1e-4 err; p50/p99 latency"
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100, help="timed steps (the workload has 100)")
+    p.add_argument("--warmup", type=int, default=3, help="untimed steps on a throwaway handle")
+    p.add_argument("--workload", default="xy21")
+    p.add_argument("--precision", default="fp64", choices=["fp64"])
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
+                   help="time budget of the oracle CPU baseline (0 disables it)")
+    p.add_argument("--no-roofline", action="store_true", help="skip the per-kernel event timing pass")
+    return p.parse_args()
+
+
+def library_baths(wl, n_steps):
+    """PT-MPOs from the library's own builder (one per distinct parameter set)."""
+    from paper_2201_05529_amd import binding as B
+    cache, out = {}, []
+    for b in wl["baths"]:
+        key = (b["alpha"], b["wc"], b["temperature"], b["k_cut"], b["cutoff"], b["coupling_op"].tobytes())
+        if key not in cache:
+            cache[key] = B.build_ptmpo(b["alpha"], b["wc"], b["temperature"], wl["dt"], n_steps, b["k_cut"],
+                                       wl["eps_tempo"], wl["xi_max"], b["coupling_op"], cutoff=b["cutoff"])
+        out.append({"site": b["site"], "tensors": cache[key]["tensors"]})
+    return out
+
+
+def make_chain(wl, baths):
+    from paper_2201_05529_amd import binding as B
+    return B.Chain(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths, chi_max=wl["chi_max"],
+                   xi_max=wl["xi_max"], eps=wl["eps"], lindblad=wl.get("lindblad"))
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle (FP64 NumPy) on the host, steps 1..S of the same workload
+    until the time budget is spent (at least one step)."""
+    from oracle import pt_tebd
+    from oracle.build import problem_from_workload
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    n = wl["n_sites"]
+    prob, _ = problem_from_workload(wl, n_steps=wl["n_steps"])
+    eng = pt_tebd.Engine(prob)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        eng.step(1)
+        for s in range(n):
+            eng.expectation(s, np.array([[1, 0], [0, -1]], dtype=np.complex128))
+        steps += 1
+        t = time.perf_counter() - t0
+        if t >= seconds or steps >= wl["n_steps"]:
+            break
+    chi = max(eng.mps.bond_dims())
+    return {"value": n * steps / t, "unit": "site-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"steps 1..{steps} of the {wl['n_steps']}-step workload from the initial state "
+                      f"(max chi reached {chi}; later steps at chi={wl['chi_max']} cost more), "
+                      f"{t:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the PT-TEBD path here "
+              f"has no multi-GPU form; see the sharding notes in the design document", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2201_05529_amd import binding as B
+    from paper_2201_05529_amd import workloads as W
+    B.lib()  # fails loudly if the HIP library is missing
+    wl = getattr(W, args.workload)()
+    n = wl["n_sites"]
+    horizon = max(args.steps, args.warmup, wl["n_steps"])
+    t0 = time.perf_counter()
+    baths = library_baths(wl, horizon)
+    t_ptmpo = time.perf_counter() - t0
+    sites = np.arange(n, dtype=np.int32)
+    ops = np.array([W.SZ] * n)
+
+    # warm-up on a throwaway handle
+    if args.warmup > 0:
+        ch = make_chain(wl, baths)
+        for _ in range(args.warmup):
+            ch.step(1)
+            ch.observe(sites, ops)
+        ch.close()
+        del ch
+
+    t0 = time.perf_counter()
+    ch = make_chain(wl, baths)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ch.step(1)
+        vals, tr = ch.observe(sites, ops)
+        if (k + 1) % 10 == 0:
+            print(f"bench: step {k + 1}/{args.steps} {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    chi, xi = ch.bond_dims()
+    value = n * args.steps / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={n} XY chain, a bath on every site, chi<={wl['chi_max']}, "
+                               f"xi<={wl['xi_max']}, dt={wl['dt']}, steps 1..{args.steps}, FP64 plain",
+                   "precision": args.precision, "max_chi": int(chi.max()), "max_xi": int(xi.max()),
+                   "trace": [tr.real, tr.imag], "ptmpo_build_s": t_ptmpo, "create_s": t_create},
+    }
+    ch.close()
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -139,6 +139,9 @@ pt_tebd_status pt_tebd_snapshot(pt_tebd_t h, void* buf, size_t* bytes);
 pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes);
 
 int32_t pt_tebd_current_step(pt_tebd_t h);
+/* Message of the handle's last error; with h == NULL, the message of the
+ * last failed pt_tebd_create on the calling thread.  The string is owned by
+ * the library and valid until the next call on the same handle (thread). */
 const char* pt_tebd_last_error(pt_tebd_t h);
 void pt_tebd_destroy(pt_tebd_t h);
 

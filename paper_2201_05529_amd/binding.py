@@ -49,6 +49,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2201_05529_amd/build_lib.py")
+        # torch ships its own HIP runtime; loading it first lets the library
+        # bind to that same runtime (one HIP/HSA runtime per process).  With
+        # the library loaded first, the process would hold two runtimes and
+        # the library's would see no device once torch initialises its own.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, dbl, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
@@ -194,7 +199,7 @@ class Chain:
         st = L.pt_tebd_create(ctypes.byref(cfg), ctypes.c_void_p(self.workspace.data_ptr()), size.value,
                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
         if st != 0:
-            raise PtTebdError(st, "pt_tebd_create")
+            raise PtTebdError(st, "pt_tebd_create: " + L.pt_tebd_last_error(None).decode())
         self.handle = handle
 
     def _check(self, st, what):

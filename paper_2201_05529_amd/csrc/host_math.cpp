@@ -417,92 +417,185 @@ struct Slot {
   std::vector<cplx> t;     // [a][x][c]
 };
 
-// Truncated SVD of a (rows x cols) matrix through the smaller Gram matrix.
+// Householder QR of a (rows x cols, row-major): a = Q R, Q rows x k with
+// orthonormal columns, R k x cols upper triangular, k = min(rows, cols).
+// Reflector H_j = I - tau_j v_j v_j^H with H_j^H x = beta e_1.
+void householder_qr(int rows, int cols, const std::vector<cplx>& a, std::vector<cplx>& q,
+                    std::vector<cplx>& r) {
+  std::vector<cplx> m(a);
+  const int k = std::min(rows, cols);
+  std::vector<std::vector<cplx>> vs(k);
+  std::vector<cplx> taus(k, cplx(0.0));
+  for (int j = 0; j < k; ++j) {
+    const cplx alpha = m[static_cast<size_t>(j) * cols + j];
+    double sig = 0.0;
+    for (int i = j + 1; i < rows; ++i) sig += std::norm(m[static_cast<size_t>(i) * cols + j]);
+    if (sig == 0.0 && alpha.imag() == 0.0) continue;  // column already reduced
+    const double nrm = std::sqrt(std::norm(alpha) + sig);
+    const double beta = alpha.real() >= 0.0 ? -nrm : nrm;
+    const cplx tau = (beta - alpha) / beta;
+    const cplx scal = 1.0 / (alpha - beta);
+    std::vector<cplx> v(rows - j);
+    v[0] = 1.0;
+    for (int i = 1; i < rows - j; ++i) v[i] = m[static_cast<size_t>(j + i) * cols + j] * scal;
+    for (int c = j; c < cols; ++c) {  // m[j:, c] <- H^H m[j:, c]
+      cplx acc(0.0);
+      for (int i = 0; i < rows - j; ++i) acc += std::conj(v[i]) * m[static_cast<size_t>(j + i) * cols + c];
+      acc *= std::conj(tau);
+      for (int i = 0; i < rows - j; ++i) m[static_cast<size_t>(j + i) * cols + c] -= v[i] * acc;
+    }
+    vs[j] = std::move(v);
+    taus[j] = tau;
+  }
+  r.assign(static_cast<size_t>(k) * cols, cplx(0.0));
+  for (int i = 0; i < k; ++i)
+    for (int c = i; c < cols; ++c) r[static_cast<size_t>(i) * cols + c] = m[static_cast<size_t>(i) * cols + c];
+  q.assign(static_cast<size_t>(rows) * k, cplx(0.0));
+  for (int i = 0; i < k; ++i) q[static_cast<size_t>(i) * k + i] = 1.0;
+  for (int j = k - 1; j >= 0; --j) {  // Q = H_0 H_1 ... H_{k-1} I
+    if (taus[j] == cplx(0.0)) continue;
+    const auto& v = vs[j];
+    for (int c = 0; c < k; ++c) {
+      cplx acc(0.0);
+      for (int i = 0; i < rows - j; ++i) acc += std::conj(v[i]) * q[static_cast<size_t>(j + i) * k + c];
+      acc *= taus[j];
+      for (int i = 0; i < rows - j; ++i) q[static_cast<size_t>(j + i) * k + c] -= v[i] * acc;
+    }
+  }
+}
+
+// One-sided Jacobi from the left on the rows of a (n x m): a = U W with U
+// unitary (n x n, accumulated from the plane rotations) and the rows of W
+// (returned in a) mutually orthogonal.  U is exactly unitary up to rounding
+// however small the row norms are, and W is never divided by anything.
+void row_jacobi(int n, int m, std::vector<cplx>& a, std::vector<cplx>& u) {
+  u.assign(static_cast<size_t>(n) * n, cplx(0.0));
+  for (int i = 0; i < n; ++i) u[static_cast<size_t>(i) * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p + 1 < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        cplx* ap = &a[static_cast<size_t>(p) * m];
+        cplx* aq = &a[static_cast<size_t>(q) * m];
+        double al = 0.0, be = 0.0;
+        cplx c(0.0);
+        for (int j = 0; j < m; ++j) {
+          al += std::norm(ap[j]);
+          be += std::norm(aq[j]);
+          c += ap[j] * std::conj(aq[j]);
+        }
+        const double ac = std::abs(c);
+        if (ac == 0.0 || ac <= 1e-16 * std::sqrt(al * be)) continue;
+        off = std::max(off, ac / std::sqrt(al * be));
+        // rows (p, q) <- G (p, q), G = [[cs, -sn ph], [sn conj(ph), cs]],
+        // with tan(theta) = t the smaller root of t^2 + 2 zeta t - 1 = 0
+        const cplx ph = c / ac;
+        const double zeta = (be - al) / (2.0 * ac);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::hypot(1.0, zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int j = 0; j < m; ++j) {
+          const cplx x = ap[j], y = aq[j];
+          ap[j] = cs * x - sn * ph * y;
+          aq[j] = sn * std::conj(ph) * x + cs * y;
+        }
+        for (int i = 0; i < n; ++i) {  // U <- U G^H
+          cplx& up = u[static_cast<size_t>(i) * n + p];
+          cplx& uq = u[static_cast<size_t>(i) * n + q];
+          const cplx x = up, y = uq;
+          up = cs * x - sn * std::conj(ph) * y;
+          uq = sn * ph * x + cs * y;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+}
+
+// Truncated SVD of a (rows x cols) matrix: QR of the matrix (or of its
+// conjugate transpose), then one-sided Jacobi on the small triangular
+// factor.  Singular values are the norms of the orthogonalised rows, the
+// left factor is a product of unitary factors, and S V^H is formed without
+// dividing by any singular value.  Truncation: the smallest rank whose
+// discarded tail has 2-norm below eps * sigma_max, then the cap.
 // Returns keep and fills u (rows x keep) and svh = S V^H (keep x cols).
 int truncated_svd(int rows, int cols, const std::vector<cplx>& m, double eps, int cap,
                   std::vector<cplx>& u, std::vector<cplx>& svh) {
-  const bool use_cols = cols <= rows;
-  const int n = use_cols ? cols : rows;
-  std::vector<cplx> g(static_cast<size_t>(n) * n, cplx(0.0));
-  if (use_cols) {
+  const int n = std::min(rows, cols);
+  std::vector<cplx> ufull, w, qf, rf, u1;
+  if (rows >= cols) {  // m = Q R, R = U1 W  ->  m = (Q U1) W
+    householder_qr(rows, cols, m, qf, rf);
+    row_jacobi(n, cols, rf, u1);
+    ufull = matmul(rows, n, n, qf.data(), u1.data());
+    w = rf;
+  } else {             // m^H = Q R  ->  m = R^H Q^H = U1 W Q^H
+    std::vector<cplx> mh(static_cast<size_t>(cols) * rows);
     for (int r = 0; r < rows; ++r)
-      for (int i = 0; i < n; ++i) {
-        const cplx ci = std::conj(m[r * cols + i]);
-        for (int j = 0; j < n; ++j) g[i * n + j] += ci * m[r * cols + j];
-      }
-  } else {
+      for (int c = 0; c < cols; ++c) mh[static_cast<size_t>(c) * rows + r] = std::conj(m[static_cast<size_t>(r) * cols + c]);
+    householder_qr(cols, rows, mh, qf, rf);  // qf cols x n, rf n x rows
+    std::vector<cplx> a(static_cast<size_t>(n) * n);
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        cplx s(0.0);
-        for (int c = 0; c < cols; ++c) s += m[i * cols + c] * std::conj(m[j * cols + c]);
-        g[i * n + j] = s;
+      for (int j = 0; j < n; ++j) a[static_cast<size_t>(i) * n + j] = std::conj(rf[static_cast<size_t>(j) * rows + i]);
+    row_jacobi(n, n, a, u1);
+    ufull = u1;
+    w.assign(static_cast<size_t>(n) * cols, cplx(0.0));  // W Q^H
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < cols; ++c) {
+        cplx acc(0.0);
+        for (int k = 0; k < n; ++k) acc += a[static_cast<size_t>(i) * n + k] * std::conj(qf[static_cast<size_t>(c) * n + k]);
+        w[static_cast<size_t>(i) * cols + c] = acc;
       }
   }
-  std::vector<double> w(n);
-  std::vector<cplx> v(static_cast<size_t>(n) * n);
-  heev(n, g.data(), w.data(), v.data());
-  // descending singular values
   std::vector<double> sv(n);
-  for (int i = 0; i < n; ++i) sv[i] = std::sqrt(std::max(w[n - 1 - i], 0.0));
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int c = 0; c < cols; ++c) acc += std::norm(w[static_cast<size_t>(i) * cols + c]);
+    sv[i] = std::sqrt(acc);
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+  std::vector<double> s(n);
+  for (int i = 0; i < n; ++i) s[i] = sv[order[i]];
   int npos = 0;
-  while (npos < n && sv[npos] > 0.0) ++npos;
+  while (npos < n && s[npos] > 0.0) ++npos;
   int keep = std::max(npos, 1);
   if (npos > 0) {
     std::vector<double> tail(npos + 1, 0.0);
-    for (int i = npos - 1; i >= 0; --i) tail[i] = tail[i + 1] + sv[i] * sv[i];
+    for (int i = npos - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
     for (int c = 1; c < npos; ++c)
-      if (std::sqrt(tail[c]) < eps * sv[0]) {
+      if (std::sqrt(tail[c]) < eps * s[0]) {
         keep = c;
         break;
       }
   }
   if (cap > 0) keep = std::min(keep, cap);
+  keep = std::min(keep, n);
   u.assign(static_cast<size_t>(rows) * keep, cplx(0.0));
   svh.assign(static_cast<size_t>(keep) * cols, cplx(0.0));
   for (int k = 0; k < keep; ++k) {
-    const int src = n - 1 - k;
-    const double s = sv[k];
-    if (use_cols) {
-      // right vector vk = column src of v; u_k = M v_k / s ; svh row = s v_k^H
-      for (int c = 0; c < cols; ++c) svh[k * cols + c] = s * std::conj(v[c * n + src]);
-      if (s > 0.0)
-        for (int r = 0; r < rows; ++r) {
-          cplx acc(0.0);
-          for (int c = 0; c < cols; ++c) acc += m[r * cols + c] * v[c * n + src];
-          u[r * keep + k] = acc / s;
-        }
-    } else {
-      // left vector uk = column src of v; svh row = u_k^H M
-      for (int r = 0; r < rows; ++r) u[r * keep + k] = v[r * n + src];
-      for (int c = 0; c < cols; ++c) {
-        cplx acc(0.0);
-        for (int r = 0; r < rows; ++r) acc += std::conj(v[r * n + src]) * m[r * cols + c];
-        svh[k * cols + c] = acc;
-      }
-    }
+    const int src = order[k];
+    for (int r = 0; r < rows; ++r) u[static_cast<size_t>(r) * keep + k] = ufull[static_cast<size_t>(r) * n + src];
+    for (int c = 0; c < cols; ++c) svh[static_cast<size_t>(k) * cols + c] = w[static_cast<size_t>(src) * cols + c];
   }
   return keep;
 }
 
 void recompress(std::vector<Slot>& mps, int lo, int hi, int d2, double eps, int cap) {
-  // right-to-left: slot j = Lf * Qr with Qr having orthonormal rows
+  // right-to-left: slot j = L Q with Q having orthonormal rows (QR of the
+  // slot's conjugate transpose, no truncation)
   for (int j = hi; j > lo; --j) {
     Slot& s = mps[j];
     const int rows = s.a, cols = d2 * s.c;
-    // SVD-based right orthonormalisation (no truncation beyond exact zeros)
-    std::vector<cplx> u, svh;
-    // factor M = U (S V^H): we want M = L Q with Q = V^H rows orthonormal;
-    // compute through the Gram of M^H (rows small): use truncated_svd on M^T layout
-    std::vector<cplx> mt(static_cast<size_t>(cols) * rows);
+    std::vector<cplx> mh(static_cast<size_t>(cols) * rows);
     for (int r = 0; r < rows; ++r)
-      for (int c = 0; c < cols; ++c) mt[c * rows + r] = std::conj(s.t[r * cols + c]);
-    // M^H = U' (S' V'^H)  ->  M = (V' S') U'^H : Q = U'^H (rows keep x cols), L = V' S'
-    const int keep = truncated_svd(cols, rows, mt, 0.0, 0, u, svh);
+      for (int c = 0; c < cols; ++c) mh[static_cast<size_t>(c) * rows + r] = std::conj(s.t[static_cast<size_t>(r) * cols + c]);
+    std::vector<cplx> qf, rf;  // M^H = Q R  ->  M = R^H Q^H
+    householder_qr(cols, rows, mh, qf, rf);
+    const int keep = std::min(rows, cols);
     std::vector<cplx> qn(static_cast<size_t>(keep) * cols), lmat(static_cast<size_t>(rows) * keep);
     for (int k = 0; k < keep; ++k)
-      for (int c = 0; c < cols; ++c) qn[k * cols + c] = std::conj(u[c * keep + k]);
+      for (int c = 0; c < cols; ++c) qn[static_cast<size_t>(k) * cols + c] = std::conj(qf[static_cast<size_t>(c) * keep + k]);
     for (int r = 0; r < rows; ++r)
-      for (int k = 0; k < keep; ++k) lmat[r * keep + k] = std::conj(svh[k * rows + r]);
+      for (int k = 0; k < keep; ++k) lmat[static_cast<size_t>(r) * keep + k] = std::conj(rf[static_cast<size_t>(k) * rows + r]);
     s.t = qn;
     s.a = keep;
     Slot& p = mps[j - 1];

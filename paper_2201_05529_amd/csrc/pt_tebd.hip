@@ -554,14 +554,23 @@ pt_tebd_status pt_tebd_workspace_size(const pt_tebd_config* cfg, size_t* bytes) 
   return PT_TEBD_OK;
 }
 
-pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes, void* stream, pt_tebd_t* out) {
-  if (!out) return PT_TEBD_EINVAL;
+namespace {
+// message of the last failed pt_tebd_create on this thread
+thread_local std::string t_create_error;
+
+pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, void* stream, pt_tebd_t* out,
+                           std::string& err) {
+  if (!out) { err = "null output pointer"; return PT_TEBD_EINVAL; }
   *out = nullptr;
-  std::string err;
   pt_tebd_status s = validate(cfg, err);
   if (s != PT_TEBD_OK) return s;
-  if (!ws) return PT_TEBD_EINVAL;
+  if (!ws) { err = "null workspace"; return PT_TEBD_EINVAL; }
   auto h = std::make_unique<pt_tebd>();
+  struct KeepMessage {  // on failure the handle is freed: keep its message
+    std::unique_ptr<pt_tebd>& h;
+    std::string& err;
+    ~KeepMessage() { if (h && !h->err.empty()) err = h->err; }
+  } keep{h, err};
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
   h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", 3));
@@ -569,7 +578,7 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
   const Caps& c = h->cap;
   const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
   const size_t need = layout(c, cfg, tl, cl, nullptr, nullptr);
-  if (bytes < need) return PT_TEBD_ENOMEM;
+  if (bytes < need) { err = "workspace smaller than pt_tebd_workspace_size"; return PT_TEBD_ENOMEM; }
   DevPtrs P;
   layout(c, cfg, tl, cl, ws, &P);
   h->n_sites = cfg->n_sites;
@@ -788,6 +797,14 @@ pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes,
   *out = h.release();
   return PT_TEBD_OK;
 }
+}  // namespace
+
+pt_tebd_status pt_tebd_create(const pt_tebd_config* cfg, void* ws, size_t bytes, void* stream, pt_tebd_t* out) {
+  std::string err;
+  const pt_tebd_status s = create_impl(cfg, ws, bytes, stream, out, err);
+  t_create_error = (s == PT_TEBD_OK) ? std::string() : err;
+  return s;
+}
 
 pt_tebd_status pt_tebd_step(pt_tebd_t h, int32_t n_steps) {
   if (!h || n_steps < 0) return PT_TEBD_EINVAL;
@@ -964,7 +981,10 @@ pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes) {
 
 int32_t pt_tebd_current_step(pt_tebd_t h) { return h ? h->step : -1; }
 
-const char* pt_tebd_last_error(pt_tebd_t h) { return h ? h->err.c_str() : "null handle"; }
+const char* pt_tebd_last_error(pt_tebd_t h) {
+  if (h) return h->err.c_str();
+  return t_create_error.empty() ? "null handle" : t_create_error.c_str();
+}
 
 void pt_tebd_destroy(pt_tebd_t h) {
   if (!h) return;

@@ -52,10 +52,9 @@ def test_library_ptmpo_equals_influence_functional(B):
     assert pt["diagonal"] and pt["bond_dims"][0] == 1 and pt["bond_dims"][-1] == 1
     got = ptmpo.contract_all_paths(pt["tensors"], 4)
     ref = _direct(eta, np.array([1.0, -1.0]), 6)
-    # the library compresses through Gram matrices (squared singular values),
-    # which resolve singular values to ~1e-8 of the largest: with eps = 1e-13
-    # the representation error is set by that floor, not by eps
-    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+    # eps = 1e-13: only the discarded tails below 1e-13 of each window's
+    # largest singular value separate the two
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
 
 
 def test_library_ptmpo_dense_coupling(B):
@@ -83,6 +82,37 @@ def test_library_ptmpo_truncated_matches_oracle_builder(B):
     a = ptmpo.contract_all_paths(lib_pt["tensors"], 4)
     b = ptmpo.contract_all_paths(ora, 4)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5
+
+
+def _random_path_sum(tensors, rng_seed):
+    """sum over all paths of prod_k P_k[x_k] v_k[x_k] for seeded random
+    complex v_k (a contraction that probes every slot of the PT-MPO)."""
+    rng = np.random.default_rng(rng_seed)
+    acc = np.ones(1, dtype=np.complex128)
+    for p in tensors:
+        v = rng.normal(size=4) + 1j * rng.normal(size=4)
+        acc = acc @ np.einsum("efx,x->ef", p, v)
+    return acc[0]
+
+
+@pytest.mark.parametrize("m,k_cut", [(14, 3), (20, 5)])
+def test_library_ptmpo_long_horizon_matches_oracle_builder(B, m, k_cut):
+    # horizons well past the memory cutoff: the window slides over the slots
+    # (the N=21 workload runs 100 steps with a 10-step memory)
+    alpha, wc, temp, dt = 0.05, 4.0, 1.0, 0.1
+    eta = bath.eta_coefficients(alpha, wc, temp, dt, k_cut)
+    lib_pt = B.build_ptmpo(alpha, wc, temp, dt, m, k_cut, 1e-7, 24, W.SZ)
+    ora = ptmpo.tempo_mpo(eta, np.array([1.0, -1.0]), m, 1e-7, xi_max=24)
+    assert lib_pt["bond_dims"] == [1] + [t.shape[1] for t in ora]
+    # trace preservation of the bath: the cap at step 0 (bond dimension 1,
+    # so free of the gauge of the inner bonds) is 1 up to the truncation
+    # (here mostly the xi cap of 24)
+    cl = ptmpo.caps(lib_pt["tensors"], 2)
+    co = ptmpo.caps(ora, 2)
+    assert abs(cl[0][0] - 1.0) < 1e-3 and abs(cl[0][0] - co[0][0]) < 1e-9
+    for seed in range(3):
+        a, b = _random_path_sum(lib_pt["tensors"], seed), _random_path_sum(ora, seed)
+        assert abs(a - b) < 1e-9 * abs(b)
 
 
 def _config(B, **over):
