@@ -54,9 +54,10 @@ typedef enum {
 
 typedef enum {
   PT_TEBD_FP64 = 0,       /* every contraction in double precision            */
-  PT_TEBD_FP32_MIXED = 1  /* contractions in single precision on the matrix
-                             cores; Gram matrices, eigensolvers, singular
-                             values, bond vectors and scale in double        */
+  PT_TEBD_FP32_MIXED = 1  /* reserved: contractions in single precision on
+                             the matrix cores with eigensolvers, singular
+                             values, bond vectors and scale in double; not
+                             available yet (create returns PT_TEBD_EINVAL)  */
 } pt_tebd_precision;
 
 /* One bath: a PT-MPO attached to one site (Appendix A.1).  Tensor k
@@ -145,9 +146,10 @@ int32_t pt_tebd_current_step(pt_tebd_t h);
 const char* pt_tebd_last_error(pt_tebd_t h);
 void pt_tebd_destroy(pt_tebd_t h);
 
-/* Enqueue n_steps time steps on n handles that share one HIP stream; the
- * bond updates of each Trotter sublayer of all handles are batched into the
- * same kernel launches. */
+/* Advance n handles by n_steps time steps each, handle after handle, each
+ * on its own stream (the bonds of one sublayer of one handle share one set
+ * of batched launches; launches are not yet shared across handles).
+ * Returns the first failing handle's status. */
 pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps);
 
 /* Host helper (not on the hot path): PT-MPO of a Gaussian bosonic bath with

@@ -4,12 +4,17 @@
 //
 //  stage 1  Householder reduction A = Q T Q^H, T real symmetric tridiagonal
 //           (reflector H_j = I - tau_j v_j v_j^H, H_j^H x = beta e_1)
-//  stage 2  every eigenvalue of T by bisection on Sturm counts
-//  stage 3  the selection rule (truncated-SVD rule of Appendix A.2, or a
-//           numerical-rank rule) fixes how many leading eigenpairs are needed
-//  stage 4  their eigenvectors of T by inverse iteration (pivoted LU of the
-//           shifted tridiagonal), re-orthogonalised within clusters of
-//           (near-)degenerate eigenvalues
+//  stage 2  T + delta I = L D L^T with D > 0 (delta a few ulps of |T|, more
+//           if needed, so the factorisation exists)
+//  stage 3  every eigenvalue of L D L^T by multisection on qd negcounts, to
+//           high relative accuracy; then the selection rule (truncated-SVD
+//           rule of Appendix A.2, or a numerical-rank rule) fixes how many
+//           leading eigenpairs are needed
+//  stage 4  their eigenvectors of T from twisted factorisations (one O(n)
+//           solve per vector); clusters of numerically equal eigenvalues
+//           get random starts, inverse iteration and Gram-Schmidt; the
+//           unresolved tail (eigenvalues at the rounding level) gets an
+//           orthonormal basis of the complement by Householder QR
 //  stage 5  (separate kernel) back-transformation V = Q Z with the stored
 //           reflectors
 //  stage 6  (separate kernels) two passes of block classical Gram-Schmidt
@@ -65,138 +70,258 @@ struct HeevJob {
   int* status;       // sticky error word (bit 1: no convergence, bit 2: non-finite)
 };
 
-constexpr int HEEV_THREADS = 256;
+constexpr int HEEV_THREADS = 256;          // back-transformation kernel
+constexpr int HEEV_SOLVE_THREADS = 1024;   // solve kernel (stages 1-4)
+
+// Number of eigenvalues of L D L^T below sigma (L unit lower bidiagonal with
+// subdiagonal l, D = diag(d) > 0), by the differential stationary qd
+// transform: s_0 = -sigma, D+_i = d_i + s_i, s_{i+1} = l_i^2 d_i s_i / D+_i
+// - sigma.  The count is the number of negative D+_i (Sylvester).  Computed
+// from the factors, the count resolves every eigenvalue to high relative
+// accuracy (a factored positive definite tridiagonal is a relatively robust
+// representation).
+__device__ inline int ldl_negcount(const double* d, const double* lld, int n, double sigma, double pivmin) {
+  int cnt = 0;
+  double s = -sigma;
+  for (int i = 0; i + 1 < n; ++i) {
+    double dp = d[i] + s;
+    if (fabs(dp) < pivmin) dp = -pivmin;
+    cnt += dp < 0.0;
+    s = lld[i] * (s / dp) - sigma;
+  }
+  double dp = d[n - 1] + s;
+  if (fabs(dp) < pivmin) dp = -pivmin;
+  cnt += dp < 0.0;
+  return cnt;
+}
 
 // ------------------------------------------------------------- stage 1..4
-__global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob* jobs) {
+__global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const HeevJob* jobs) {
+  constexpr int NT = HEEV_SOLVE_THREADS;
   const HeevJob& J = jobs[blockIdx.x];
   const int n = *J.n_ptr;
-  const int tid = threadIdx.x;
-  __shared__ double red[HEEV_THREADS / 64];
-  __shared__ double2 sv[1024];  // current reflector v (n <= 1024)
-  __shared__ double2 sw[1024];  // y then w
-  __shared__ double2 s_tau;
-  __shared__ double s_beta;
-  __shared__ int s_nvec;
   if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
+  const int tid = threadIdx.x;
+  __shared__ double buf[8192];     // stage 1: two v, w, partial sums; later: d, l, l d, l^2 d, mu, tau
+  __shared__ double red[NT / 64];
+  __shared__ double2 s_tau;
+  __shared__ double s_beta, s_delta, s_tnorm;
+  __shared__ int s_nvec, s_ok;
   double2* A = J.a;
   const int lda = J.lda;
+  const int nc = J.n_cap;
   double* dd = J.tri;              // diagonal of T
-  double* ee = J.tri + J.n_cap;    // off-diagonal of T (ee[i] couples i, i+1)
-  double2* taus = reinterpret_cast<double2*>(J.tri + 2 * J.n_cap);
+  double* ee = J.tri + nc;         // off-diagonal of T (ee[i] couples i, i+1)
+  double2* taus = reinterpret_cast<double2*>(J.tri + 2 * nc);
 
-  // -------- stage 1: reduction to tridiagonal form
-  for (int j = 0; j + 1 < n; ++j) {
-    const int m = n - j - 1;
-    // column below the diagonal: x_i = A[j+1+i][j]
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += HEEV_THREADS) part += cabs2<double>(A[(size_t)(j + 1 + i) * lda + j]);
-    const double sig2 = block_sum(part, red);
-    if (tid == 0) {
-      const double2 alpha = A[(size_t)(j + 1) * lda + j];
-      double2 tau = mk<double>(0.0, 0.0);
-      double beta = alpha.x;
-      if (!(sig2 == 0.0 && alpha.y == 0.0)) {
-        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
-        beta = alpha.x >= 0.0 ? -nrm : nrm;
-        tau = mk<double>((beta - alpha.x) / beta, -alpha.y / beta);
+  // -------- stage 1: reduction to real tridiagonal form, T = Q^H A Q.
+  // Both triangles of the trailing block are kept.  The rank-2 update of
+  // step j is not applied at once: step j+1 first forms its own row from the
+  // pending update, then one fused pass over the trailing block applies the
+  // pending update and accumulates the next matrix-vector product, so every
+  // element is read and written once per step.  Each pass is coalesced
+  // along rows (thread c of a row group owns column c).
+  {
+    double2* vbuf0 = reinterpret_cast<double2*>(buf);
+    double2* vbuf1 = vbuf0 + 1024;
+    double2* sw = vbuf1 + 1024;   // pending w, then the new w
+    double2* part = sw + 1024;
+    double2* vp = vbuf0;          // pending v (offset j at step j)
+    double2* vc = vbuf1;          // current v
+    bool pending = false;
+    for (int j = 0; j + 1 < n; ++j) {
+      const int m = n - j - 1, off = j + 1;
+      // (a) row j of the updated matrix: x = conj(row) below the diagonal
+      for (int i = tid; i < m; i += NT) {
+        double2 val = A[(size_t)j * lda + off + i];
+        if (pending) {
+          const double2 t1 = cmul<double>(sw[0], cconj<double>(vp[i + 1]));
+          const double2 t2 = cmul<double>(vp[0], cconj<double>(sw[i + 1]));
+          val.x -= t1.x + t2.x;
+          val.y -= t1.y + t2.y;
+        }
+        vc[i] = cconj<double>(val);
       }
-      s_tau = tau;
-      s_beta = beta;
-      taus[j] = tau;
-      ee[j] = beta;
-    }
-    __syncthreads();
-    const double2 tau = s_tau;
-    const double beta = s_beta;
-    const bool active = !(tau.x == 0.0 && tau.y == 0.0);
-    // v = x / (alpha - beta), v_0 = 1
-    double2 scal = mk<double>(0.0, 0.0);
-    {
-      const double2 alpha = A[(size_t)(j + 1) * lda + j];
-      const double2 den = mk<double>(alpha.x - beta, alpha.y);
-      const double dn = den.x * den.x + den.y * den.y;
-      if (active && dn > 0.0) scal = mk<double>(den.x / dn, -den.y / dn);
-    }
-    for (int i = tid; i < m; i += HEEV_THREADS) {
-      double2 vi;
-      if (i == 0) vi = mk<double>(1.0, 0.0);
-      else vi = active ? cmul<double>(A[(size_t)(j + 1 + i) * lda + j], scal) : mk<double>(0.0, 0.0);
-      sv[i] = vi;
-      J.refl[(size_t)j * J.n_cap + i] = vi;
-    }
-    __syncthreads();
-    if (active) {
-      // y = tau * A22 v : one wave per row (coalesced along the row)
-      const int lane = tid & 63, wid = tid >> 6;
-      for (int r = wid; r < m; r += HEEV_THREADS / 64) {
-        const double2* row = A + (size_t)(j + 1 + r) * lda + (j + 1);
+      if (tid == 0) {
+        double a = A[(size_t)j * lda + j].x;
+        if (pending) a -= 2.0 * (sw[0].x * vp[0].x + sw[0].y * vp[0].y);
+        dd[j] = a;
+      }
+      __syncthreads();
+      double p = 0.0;
+      for (int i = 1 + tid; i < m; i += NT) p += cabs2<double>(vc[i]);
+      const double sig2 = block_sum(p, red);
+      if (tid == 0) {
+        const double2 alpha = vc[0];
+        double2 tau = mk<double>(0.0, 0.0);
+        double beta = alpha.x;
+        if (!(sig2 == 0.0 && alpha.y == 0.0)) {
+          const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+          beta = alpha.x >= 0.0 ? -nrm : nrm;
+          tau = mk<double>((beta - alpha.x) / beta, -alpha.y / beta);
+        }
+        s_tau = tau;
+        s_beta = beta;
+        taus[j] = tau;
+        ee[j] = beta;
+      }
+      __syncthreads();
+      const double2 tau = s_tau;
+      const double beta = s_beta;
+      const bool active = !(tau.x == 0.0 && tau.y == 0.0);
+      double2 scal = mk<double>(0.0, 0.0);
+      {
+        const double2 alpha = vc[0];
+        const double2 den = mk<double>(alpha.x - beta, alpha.y);
+        const double dn = den.x * den.x + den.y * den.y;
+        if (active && dn > 0.0) scal = mk<double>(den.x / dn, -den.y / dn);
+      }
+      __syncthreads();  // everyone has read vc[0]
+      for (int i = tid; i < m; i += NT) {
+        double2 vi;
+        if (i == 0) vi = mk<double>(1.0, 0.0);
+        else vi = active ? cmul<double>(vc[i], scal) : mk<double>(0.0, 0.0);
+        vc[i] = vi;
+        J.refl[(size_t)j * nc + i] = vi;
+      }
+      __syncthreads();
+      // (b) fused pass: A22 -= pending update; part = conj(A22)^T v
+      const int groups = max(1, NT / m);
+      const int c = tid % m, g = tid / m;
+      if (g < groups) {
         double2 acc = mk<double>(0.0, 0.0);
-        for (int c = lane; c < m; c += 64) cfma<double>(acc, row[c], sv[c]);
-        acc.x = warp_sum(acc.x);
-        acc.y = warp_sum(acc.y);
-        if (lane == 0) sw[r] = cmul<double>(tau, acc);
+        if (pending) {
+          const double2 vpc = cconj<double>(vp[c + 1]), wpc = cconj<double>(sw[c + 1]);
+#pragma unroll 4
+          for (int r = g; r < m; r += groups) {
+            double2* dst = A + (size_t)(off + r) * lda + off + c;
+            double2 val = *dst;
+            const double2 t1 = cmul<double>(sw[r + 1], vpc);
+            const double2 t2 = cmul<double>(vp[r + 1], wpc);
+            val.x -= t1.x + t2.x;
+            val.y -= t1.y + t2.y;
+            *dst = val;
+            cfmaconj<double>(acc, val, vc[r]);
+          }
+        } else {
+#pragma unroll 4
+          for (int r = g; r < m; r += groups) cfmaconj<double>(acc, A[(size_t)(off + r) * lda + off + c], vc[r]);
+        }
+        part[g * m + c] = acc;
       }
       __syncthreads();
-      // w = y - 1/2 Re(conj(tau) v^H y) v
-      double2 p = mk<double>(0.0, 0.0);
-      for (int i = tid; i < m; i += HEEV_THREADS) cfmaconj<double>(p, sv[i], sw[i]);
-      const double vhy_re = block_sum(p.x, red);
-      const double vhy_im = block_sum(p.y, red);
-      const double half = 0.5 * (tau.x * vhy_re + tau.y * vhy_im);  // Re(conj(tau) vhy)
-      __syncthreads();
-      for (int i = tid; i < m; i += HEEV_THREADS) sw[i] = csub<double>(sw[i], cscale<double>(sv[i], half));
-      __syncthreads();
-      // A22 -= w v^H + v w^H
-      for (int e = tid; e < m * m; e += HEEV_THREADS) {
-        const int r = e / m, c = e - r * m;
-        double2* dst = A + (size_t)(j + 1 + r) * lda + (j + 1 + c);
-        double2 val = *dst;
-        const double2 t1 = cmul<double>(sw[r], cconj<double>(sv[c]));
-        const double2 t2 = cmul<double>(sv[r], cconj<double>(sw[c]));
-        val.x -= t1.x + t2.x;
-        val.y -= t1.y + t2.y;
-        *dst = val;
+      // (c) w = tau y - 1/2 Re(conj(tau) v^H tau y) v becomes the pending update
+      double2 pv = mk<double>(0.0, 0.0);
+      double2 y = mk<double>(0.0, 0.0);
+      if (tid < m) {
+        for (int q = 0; q < groups; ++q) y = cadd<double>(y, part[q * m + tid]);
+        y = cmul<double>(tau, y);
+        cfmaconj<double>(pv, vc[tid], y);
       }
+      const double vhy_re = block_sum(pv.x, red);
+      const double vhy_im = block_sum(pv.y, red);
+      const double half = 0.5 * (tau.x * vhy_re + tau.y * vhy_im);
+      if (tid < m) sw[tid] = csub<double>(y, cscale<double>(vc[tid], half));
+      __syncthreads();
+      double2* t = vp;
+      vp = vc;
+      vc = t;
+      pending = true;
     }
-    __syncthreads();
-  }
-  for (int i = tid; i < n; i += HEEV_THREADS) dd[i] = A[(size_t)i * lda + i].x;
-  if (tid == 0) ee[n - 1] = 0.0;
-  __syncthreads();
-
-  // -------- stage 2: eigenvalues by bisection (ascending index k)
-  double tnorm = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double r = fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
-    tnorm = fmax(tnorm, r);
-  }
-  const double glo = -tnorm, ghi = tnorm;
-  const double pivmin = fmax(1e-300, 1e-290 * tnorm * tnorm);
-  const double abstol = 2.2e-16 * tnorm * 0.5 + 1e-300;
-  for (int k = tid; k < n; k += HEEV_THREADS) {
-    double lo = glo - 1e-300, hi = ghi + 1e-300;
-    for (int it = 0; it < 80; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= fmax(abstol, 4.4e-16 * fmax(fabs(lo), fabs(hi)))) break;
-      int cnt = 0;
-      double q = dd[0] - mid;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      for (int i = 1; i < n; ++i) {
-        q = dd[i] - mid - ee[i - 1] * ee[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-      }
-      if (cnt > k) hi = mid;   // more than k eigenvalues below mid
-      else lo = mid;
+    if (tid == 0) {
+      double a = A[(size_t)(n - 1) * lda + (n - 1)].x;
+      if (pending) a -= 2.0 * (sw[0].x * vp[0].x + sw[0].y * vp[0].y);
+      dd[n - 1] = a;
+      ee[n - 1] = 0.0;
     }
-    // store descending: position n-1-k
-    J.w[n - 1 - k] = 0.5 * (lo + hi);
   }
   __syncthreads();
 
-  // -------- stage 3: selection rule (thread 0)
+  // -------- stage 2: T + delta I = L D L^T with D > 0
+  double* d = buf;
+  double* l = buf + 1024;
+  double* ld = buf + 2048;
+  double* lld = buf + 3072;
+  double* mu = buf + 4096;
+  if (tid == 0) {
+    double tn = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+      tn = fmax(tn, r);
+    }
+    s_tnorm = tn;
+    int ok = 0;
+    double delta = fmax(8.0 * n * 2.2e-16 * tn, 1e-300);
+    if (tn > 0.0) {
+      for (int attempt = 0; attempt < 64 && !ok; ++attempt) {
+        ok = 1;
+        double di = dd[0] + delta;
+        for (int i = 0; i < n; ++i) {
+          if (!(di > 1e-300 * fmax(tn, 1.0))) { ok = 0; break; }
+          d[i] = di;
+          if (i + 1 < n) {
+            const double li = ee[i] / di;
+            l[i] = li;
+            ld[i] = li * di;
+            lld[i] = li * li * di;
+            di = (dd[i + 1] + delta) - li * ee[i];
+          }
+        }
+        if (!ok) delta = fmin(delta * 8.0, 4.0 * tn);
+      }
+    }
+    s_delta = delta;
+    s_ok = ok;
+  }
+  __syncthreads();
+  const double tnorm = s_tnorm;
+  const double delta = s_delta;
+  if (!s_ok) {
+    // zero matrix (or a factorisation that never became definite): every
+    // eigenvalue is taken as zero and Z = I
+    for (int i = tid; i < n; i += NT) {
+      J.w[i] = 0.0;
+      mu[i] = 0.0;
+    }
+    if (tnorm > 0.0 && tid == 0) atomicOr(J.status, 1);
+  } else {
+    // -------- stage 3: eigenvalues of L D L^T by multisection, four
+    // threads per eigenvalue, geometric splits (relative accuracy)
+    const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
+    const int q = tid & 3;
+    for (int k0 = 0; k0 < n; k0 += NT / 4) {
+      const int k = k0 + (tid >> 2);
+      double lo = 1e-300 * (tnorm + delta), hi = 1.01 * (tnorm + delta) + 1e-300;
+      if (k < n) {
+        for (int it = 0; it < 120; ++it) {
+          if (hi - lo <= 4.4e-16 * hi) break;
+          const bool geo = lo > 0.0 && hi > 4.0 * lo;
+          const double f = (q + 1) * 0.2;
+          const double x = geo ? lo * exp(f * log(hi / lo)) : lo + f * (hi - lo);
+          const int cnt = ldl_negcount(d, lld, n, x, pivmin);
+          // gather the four (x, cnt) pairs of this quad
+          double nlo = lo, nhi = hi;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double xr = __shfl(x, ((threadIdx.x & 63) & ~3) + r, 64);
+            const int cr = __shfl(cnt, ((threadIdx.x & 63) & ~3) + r, 64);
+            if (cr <= k) nlo = fmax(nlo, xr);
+            else nhi = fmin(nhi, xr);
+          }
+          lo = nlo;
+          hi = nhi;
+        }
+      }
+      if (k < n && q == 0) {
+        const double m_k = 0.5 * (lo + hi);
+        mu[k] = m_k;
+        J.w[n - 1 - k] = m_k - delta;
+      }
+    }
+  }
+  __syncthreads();
+
+  // -------- stage 3b: selection rule (thread 0)
   if (tid == 0) {
     const double* w = J.w;
     int nvec = 0;
@@ -235,183 +360,207 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_solve_kernel(const HeevJob*
   __syncthreads();
   const int nvec = s_nvec;
 
-  // -------- stage 4: inverse iteration, one thread per eigenvector
-  // interleaved workspace: array a, row i, vector k at work[(a * n_cap + i) * n_cap + k]
-  const int nc = J.n_cap;
+  // -------- stage 4: eigenvectors of T by twisted factorisations of
+  // L D L^T - mu I (one thread per vector).  Top-down: D+_i = d_i + s_i,
+  // l+_i = l_i d_i / D+_i; bottom-up: D-_i = l_{i-1}^2 d_{i-1} + p_i,
+  // u-_i = l_i d_i / D-_{i+1}, p_i = d_i p_{i+1} / D-_{i+1} - mu.  The twist
+  // index r minimises |gamma_r| = |s_r + p_r + mu|; z_r = 1 and
+  // z_i = -l+_i z_{i+1} above r, z_{i+1} = -u-_i z_i below.  With mu accurate
+  // to high relative accuracy the vector's error is O(n eps) / relgap, so
+  // vectors of distinct eigenvalues come out orthogonal without any
+  // reorthogonalisation.  Per-vector arrays interleave by vector index.
   auto W = [&](int arr, int i, int k) -> double& { return J.work[((size_t)arr * nc + i) * nc + k]; };
-  for (int k = tid; k < nvec; k += HEEV_THREADS) {
-    const double lam = J.w[k];
-    // shifted tridiagonal: dl = ee (sub), dg = dd - lam, du = ee (super), du2 = 0
-    for (int i = 0; i < n; ++i) {
-      W(0, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // dl
-      W(1, i, k) = dd[i] - lam;                // dg
-      W(2, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // du
-      W(3, i, k) = 0.0;                        // du2
-      W(4, i, k) = 0.0;                        // pivot flag
+  auto Z = [&](int i, int k) -> double& { return J.z[(size_t)i * nc + k]; };
+  if (!s_ok) {
+    for (int e = tid; e < n * nvec; e += NT) {
+      const int i = e / nvec, k = e - i * nvec;
+      Z(i, k) = (i == k) ? 1.0 : 0.0;
     }
+    return;
+  }
+  const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
+  // eigenvalues within the rounding level of the reduction (lambda <= delta,
+  // a few n eps |T|) are not resolved: their vectors are any orthonormal
+  // basis of the complement of the resolved ones (stage 4c).  They form a
+  // tail of the descending order.
+  int nres = 0;
+  while (nres < nvec && J.w[nres] > delta) ++nres;
+  for (int k = tid; k < nres; k += NT) {
+    const double m_k = mu[n - 1 - k];
+    // top-down (stationary)
+    double s = -m_k;
     for (int i = 0; i + 1 < n; ++i) {
-      const double di = W(1, i, k), li = W(0, i, k);
-      if (fabs(di) >= fabs(li)) {
-        const double f = (di != 0.0) ? li / di : 0.0;
-        W(0, i, k) = f;
-        W(1, i + 1, k) -= f * W(2, i, k);
-        W(3, i, k) = 0.0;
-        W(4, i, k) = 0.0;
-      } else {
-        const double f = di / li;
-        W(1, i, k) = li;
-        W(0, i, k) = f;
-        const double tmp = W(2, i, k);
-        W(2, i, k) = W(1, i + 1, k);
-        W(1, i + 1, k) = tmp - f * W(1, i + 1, k);
-        if (i + 2 < n) {
-          W(3, i, k) = W(2, i + 1, k);
-          W(2, i + 1, k) = -f * W(2, i + 1, k);
-        }
-        W(4, i, k) = 1.0;
-      }
+      W(1, i, k) = s;
+      double dp = d[i] + s;
+      if (fabs(dp) < pivmin) dp = dp < 0.0 ? -pivmin : pivmin;
+      W(0, i, k) = ld[i] / dp;
+      s = lld[i] * (s / dp) - m_k;
     }
-    const double tiny = fmax(2.2e-16 * tnorm, 1e-300);
-    for (int i = 0; i < n; ++i)
-      if (fabs(W(1, i, k)) < tiny) W(1, i, k) = W(1, i, k) >= 0.0 ? tiny : -tiny;
-    // start vector (deterministic pseudo-random, distinct per k)
-    for (int i = 0; i < n; ++i) W(5, i, k) = u01(splitmix64(0x51ED2701ull * (k + 1) + i)) - 0.5;
-    for (int it = 0; it < 3; ++it) {
-      // forward (apply P and L)
-      for (int i = 0; i + 1 < n; ++i) {
-        if (W(4, i, k) != 0.0) {
-          const double t = W(5, i, k);
-          W(5, i, k) = W(5, i + 1, k);
-          W(5, i + 1, k) = t;
-        }
-        W(5, i + 1, k) -= W(0, i, k) * W(5, i, k);
-      }
-      // backward (U)
-      for (int i = n - 1; i >= 0; --i) {
-        double s = W(5, i, k);
-        if (i + 1 < n) s -= W(2, i, k) * W(6, i + 1, k);
-        if (i + 2 < n) s -= W(3, i, k) * W(6, i + 2, k);
-        W(6, i, k) = s / W(1, i, k);
-      }
-      double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += W(6, i, k) * W(6, i, k);
-      nrm = sqrt(nrm);
-      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = 0; i < n; ++i) W(5, i, k) = W(6, i, k) * inv;
+    W(1, n - 1, k) = s;
+    // bottom-up (progressive) with the twist index
+    double p = d[n - 1] - m_k;
+    double gmin = fabs(W(1, n - 1, k) + p + m_k);
+    int r = n - 1;
+    for (int i = n - 2; i >= 0; --i) {
+      double dm = lld[i] + p;
+      if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
+      const double t = d[i] / dm;
+      W(2, i, k) = l[i] * t;
+      p = p * t - m_k;
+      const double g = fabs(W(1, i, k) + p + m_k);
+      if (g < gmin) { gmin = g; r = i; }
+    }
+    // solve
+    double z = 1.0, nrm = 1.0;
+    Z(r, k) = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      z = -W(0, i, k) * z;
+      Z(i, k) = z;
+      nrm += z * z;
+    }
+    z = 1.0;
+    for (int i = r; i + 1 < n; ++i) {
+      z = -W(2, i, k) * z;
+      Z(i + 1, k) = z;
+      nrm += z * z;
+    }
+    const double inv = (nrm > 0.0 && nrm < 1e300) ? 1.0 / sqrt(nrm) : 0.0;
+    if (inv > 0.0) {
+      for (int i = 0; i < n; ++i) Z(i, k) *= inv;
+    } else {  // overflow: fall back to the unit vector at the twist index
+      for (int i = 0; i < n; ++i) Z(i, k) = (i == r) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
-  // clusters of (near-)degenerate selected eigenvalues: orthogonalise each
-  // member against its predecessors and iterate again (wave 0)
-  if (tid < 64) {
-    const int lane = tid;
-    // clusters are formed among well-determined eigenvalues only
-    // (lambda > 1e-12 |lambda_0|); below that the eigenvectors of a Gram
-    // matrix are not resolved in double precision anyway
-    const double gap_tol = 1e-10 * fmax(fabs(J.w[0]), 1e-300);
-    const double floor_val = 1e-12 * fabs(J.w[0]);
-    int nclu = 0;
-    while (nclu < nvec && J.w[nclu] > floor_val) ++nclu;
-    int start = 0;
-    for (int k = 1; k <= nclu; ++k) {
-      const bool brk = (k == nclu) || (fabs(J.w[k - 1] - J.w[k]) > gap_tol);
-      if (!brk) continue;
-      for (int j = start + 1; j < k; ++j) {
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int p = start; p < j; ++p) {
-            double dot = 0.0;
-            for (int i = lane; i < n; i += 64) dot += W(5, i, p) * W(5, i, j);
-            dot = warp_sum(dot);
-            for (int i = lane; i < n; i += 64) W(5, i, j) -= dot * W(5, i, p);
-          }
-          // one more inverse-iteration solve with the member's own factors
-          if (lane == 0) {
-            for (int i = 0; i + 1 < n; ++i) {
-              if (W(4, i, j) != 0.0) {
-                const double t = W(5, i, j);
-                W(5, i, j) = W(5, i + 1, j);
-                W(5, i + 1, j) = t;
-              }
-              W(5, i + 1, j) -= W(0, i, j) * W(5, i, j);
-            }
-            for (int i = n - 1; i >= 0; --i) {
-              double s = W(5, i, j);
-              if (i + 1 < n) s -= W(2, i, j) * W(6, i + 1, j);
-              if (i + 2 < n) s -= W(3, i, j) * W(6, i + 2, j);
-              W(6, i, j) = s / W(1, i, j);
-            }
-            for (int i = 0; i < n; ++i) W(5, i, j) = W(6, i, j);
-          }
-          __builtin_amdgcn_wave_barrier();
-          for (int p = start; p < j; ++p) {
-            double dot = 0.0;
-            for (int i = lane; i < n; i += 64) dot += W(5, i, p) * W(5, i, j);
-            dot = warp_sum(dot);
-            for (int i = lane; i < n; i += 64) W(5, i, j) -= dot * W(5, i, p);
-          }
-          double nrm = 0.0;
-          for (int i = lane; i < n; i += 64) nrm += W(5, i, j) * W(5, i, j);
-          nrm = warp_sum(nrm);
-          const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-          for (int i = lane; i < n; i += 64) W(5, i, j) *= inv;
-        }
-      }
-      start = k;
-    }
-  }
-  __syncthreads();
-  // vectors of eigenvalues below the resolution floor (and any later ones)
-  // are undetermined individually; orthonormalise them against every
-  // earlier vector (modified Gram-Schmidt, two passes, whole workgroup) so
-  // the eigenvector matrix is unitary -- any orthonormal basis of that
-  // subspace is equally valid.
+
+  // -------- stage 4b: clusters of numerically equal eigenvalues (relative
+  // gap below 1e-9).  Twisted vectors of equal mu coincide, so every member
+  // after the first restarts from a seeded random vector, takes two
+  // inverse-iteration solves with its own top-down factors, and is
+  // orthogonalised against the earlier members (one wave per cluster).
   {
-    __shared__ double dots[1024];
-    __shared__ int s_j0;
-    if (tid == 0) {
-      const double floor_val = 1e-10 * fabs(J.w[0]);
-      int j0 = 0;
-      while (j0 < nvec && J.w[j0] > floor_val) ++j0;
-      s_j0 = j0;
+    const double rgap = 1e-9;
+    auto same = [&](int a, int b) {  // a, b descending-order indices
+      const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
+      return fabs(ma - mb) <= rgap * fmax(fabs(ma), fabs(mb));
+    };
+    // pivots of the (nearly) singular shifted matrix are floored at
+    // eps |T|, as in inverse iteration: the solve then amplifies the
+    // eigenspace without overflowing
+    const double pfloor = fmax(2.2e-16 * tnorm, pivmin);
+    // members: k with k > 0 and same(k - 1, k)
+    for (int k = tid; k < nres; k += NT) {
+      if (k == 0 || !same(k - 1, k)) continue;
+      const double m_k = mu[n - 1 - k];
+      // top-down factors of L D L^T - mu I with floored pivots: W(0) = l+,
+      // W(1) = D+
+      double s = -m_k;
+      for (int i = 0; i < n; ++i) {
+        double dp = d[i] + s;
+        if (fabs(dp) < pfloor) dp = dp < 0.0 ? -pfloor : pfloor;
+        W(1, i, k) = dp;
+        if (i + 1 < n) {
+          W(0, i, k) = ld[i] / dp;
+          s = lld[i] * (s / dp) - m_k;
+        }
+      }
+      for (int i = 0; i < n; ++i) Z(i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
+      for (int it = 0; it < 2; ++it) {
+        // (L+ D+ L+^T) y = z: forward with L+, divide by D+, backward with L+^T
+        for (int i = 0; i + 1 < n; ++i) Z(i + 1, k) -= W(0, i, k) * Z(i, k);
+        for (int i = 0; i < n; ++i) Z(i, k) /= W(1, i, k);
+        for (int i = n - 2; i >= 0; --i) Z(i, k) -= W(0, i, k) * Z(i + 1, k);
+        double nr = 0.0;
+        for (int i = 0; i < n; ++i) nr += Z(i, k) * Z(i, k);
+        const double inv = (nr > 0.0 && nr < 1e300) ? 1.0 / sqrt(nr) : 0.0;
+        for (int i = 0; i < n; ++i) Z(i, k) *= inv;
+      }
     }
     __syncthreads();
-    for (int j = max(s_j0, 1); j < nvec; ++j) {
-      for (int attempt = 0; attempt < 2; ++attempt) {
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int i = tid; i < j; i += HEEV_THREADS) {
-            double acc = 0.0;
-            for (int r = 0; r < n; ++r) acc += W(5, r, i) * W(5, r, j);
-            dots[i] = acc;
+    const int lane = tid & 63, wid = tid >> 6;
+    // cluster starts, handed out round-robin to the waves
+    int cl = 0;
+    for (int k = 0; k < nres; ++k) {
+      if (k > 0 && same(k - 1, k)) continue;  // not a start
+      int e = k + 1;
+      while (e < nres && same(e - 1, e)) ++e;
+      if (e - k >= 2 && (cl++ % (NT / 64)) == wid) {
+        for (int j = k + 1; j < e; ++j) {
+          for (int pass = 0; pass < 2; ++pass) {
+            for (int q2 = k; q2 < j; ++q2) {
+              double dot = 0.0;
+              for (int i = lane; i < n; i += 64) dot += Z(i, q2) * Z(i, j);
+              dot = warp_sum(dot);
+              for (int i = lane; i < n; i += 64) Z(i, j) -= dot * Z(i, q2);
+            }
+            double nr = 0.0;
+            for (int i = lane; i < n; i += 64) nr += Z(i, j) * Z(i, j);
+            nr = warp_sum(nr);
+            const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+            for (int i = lane; i < n; i += 64) Z(i, j) *= inv;
           }
-          __syncthreads();
-          for (int r = tid; r < n; r += HEEV_THREADS) {
-            double acc = W(5, r, j);
-            for (int i = 0; i < j; ++i) acc -= dots[i] * W(5, r, i);
-            W(5, r, j) = acc;
-          }
-          __syncthreads();
         }
-        double part = 0.0;
-        for (int r = tid; r < n; r += HEEV_THREADS) part += W(5, r, j) * W(5, r, j);
-        const double nrm = sqrt(block_sum(part, red));
-        if (nrm > 1e-8 || attempt == 1) {
-          const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-          for (int r = tid; r < n; r += HEEV_THREADS) W(5, r, j) *= inv;
-          __syncthreads();
-          break;
-        }
-        // nearly parallel to the earlier vectors: restart from a fresh vector
-        for (int r = tid; r < n; r += HEEV_THREADS)
-          W(5, r, j) = u01(splitmix64(0xC2B2AE3D27D4EB4Full * (j + 1) + r)) - 0.5;
-        __syncthreads();
       }
     }
   }
+  if (nres >= nvec) return;
   __syncthreads();
-  // publish Z (row i, column k)
-  for (int e = tid; e < n * nvec; e += HEEV_THREADS) {
-    const int i = e / nvec, k = e - i * nvec;
-    J.z[(size_t)i * nc + k] = W(5, i, k);
+
+  // -------- stage 4c: unresolved tail.  Householder QR of a copy of the
+  // resolved vectors Z_h (n x h, orthonormal): H_{h-1} ... H_0 Z_h = [R; 0].
+  // Then Q = H_0 ... H_{h-1} and its columns h, h+1, ... are an orthonormal
+  // basis of the complement; column c = Q e_c is built by one thread
+  // applying the reflectors to e_c.  Reflector j is kept in W(3, i >= j, j),
+  // the copy of Z_h in W(4), tau_j in LDS.
+  {
+    double* rtau = buf + 5120;  // <= 1024 reflectors
+    const int h = nres;
+    for (int e = tid; e < n * h; e += NT) {
+      const int i = e / h, c = e - i * h;
+      W(4, i, c) = Z(i, c);
+    }
+    __syncthreads();
+    for (int j = 0; j < h; ++j) {
+      double part = 0.0;
+      for (int i = j + 1 + tid; i < n; i += NT) part += W(4, i, j) * W(4, i, j);
+      const double sig2 = block_sum(part, red);
+      if (tid == 0) {
+        const double alpha = W(4, j, j);
+        double tau = 0.0, beta = alpha;
+        if (sig2 > 0.0) {
+          const double nrm = sqrt(alpha * alpha + sig2);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+        }
+        rtau[j] = tau;
+        s_beta = (tau != 0.0) ? 1.0 / (alpha - beta) : 0.0;
+      }
+      __syncthreads();
+      const double scl = s_beta;
+      const double tau = rtau[j];
+      for (int i = j + tid; i < n; i += NT) W(3, i, j) = (i == j) ? 1.0 : W(4, i, j) * scl;
+      __syncthreads();
+      if (tau != 0.0) {
+        for (int c = j + 1 + tid; c < h; c += NT) {  // one thread per column
+          double dot = 0.0;
+          for (int i = j; i < n; ++i) dot += W(3, i, j) * W(4, i, c);
+          dot *= tau;
+          for (int i = j; i < n; ++i) W(4, i, c) -= dot * W(3, i, j);
+        }
+      }
+      __syncthreads();
+    }
+    for (int c = h + tid; c < nvec; c += NT) {
+      for (int i = 0; i < n; ++i) Z(i, c) = (i == c) ? 1.0 : 0.0;
+      for (int j = h - 1; j >= 0; --j) {
+        const double tau = rtau[j];
+        if (tau == 0.0) continue;
+        double dot = 0.0;
+        for (int i = j; i < n; ++i) dot += W(3, i, j) * Z(i, c);
+        dot *= tau;
+        for (int i = j; i < n; ++i) Z(i, c) -= dot * W(3, i, j);
+      }
+    }
   }
 }
 

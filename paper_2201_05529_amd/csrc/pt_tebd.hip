@@ -107,7 +107,8 @@ Caps compute_caps(const pt_tebd_config* cfg, int oversample) {
   c.xi_cap = std::max(1, cfg->xi_max);
   c.nb = 4 * c.chi_cap;
   c.dn = 4 * c.nb;
-  c.kc = std::min(c.dn, c.chi_cap + oversample);
+  // the eigensolver holds one problem of size <= 1024 per workgroup
+  c.kc = std::min({c.dn, c.chi_cap + oversample, 1024});
   c.nh = std::max(c.nb, c.kc);
   c.n_slots = cfg->n_sites / 2;  // max(#even, #odd) bonds = floor(N/2)
   c.gam_cap = (long long)c.chi_cap * 4 * c.xi_cap * c.chi_cap;
@@ -267,7 +268,8 @@ pt_tebd_status validate(const pt_tebd_config* cfg, std::string& err) {
   if (!(cfg->svd_rel_cutoff >= 0.0) || !(cfg->svd_rel_cutoff < 1.0)) { err = "svd_rel_cutoff must be in [0, 1)"; return PT_TEBD_EINVAL; }
   if (!cfg->h_site || !cfg->rho0 || (cfg->n_sites > 1 && !cfg->h_bond)) { err = "missing h_site, h_bond or rho0"; return PT_TEBD_EINVAL; }
   if (cfg->n_lindblad < 0 || (cfg->n_lindblad > 0 && !cfg->lindblad)) { err = "bad lindblad"; return PT_TEBD_EINVAL; }
-  if (cfg->precision != PT_TEBD_FP64 && cfg->precision != PT_TEBD_FP32_MIXED) { err = "bad precision"; return PT_TEBD_EINVAL; }
+  if (cfg->precision == PT_TEBD_FP32_MIXED) { err = "the mixed-precision form is not available yet"; return PT_TEBD_EINVAL; }
+  if (cfg->precision != PT_TEBD_FP64) { err = "bad precision"; return PT_TEBD_EINVAL; }
   if (cfg->n_baths < 0 || cfg->n_baths > cfg->n_sites || (cfg->n_baths > 0 && !cfg->baths)) { err = "bad baths"; return PT_TEBD_EINVAL; }
   const int N = cfg->n_sites;
   auto herm = [](const double* m, int n) {
@@ -346,7 +348,7 @@ void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int
 int elem_blocks(long long n);
 
 void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
-  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_THREADS, 0, st>>>(jobs);
+  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs);
   dim3 grid((n_cap + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, n_jobs);
   const size_t shm = (size_t)n_cap * ptt::HEEV_BT_COLS * sizeof(double2);
   ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, shm, st>>>(jobs);

@@ -84,6 +84,24 @@ def test_heev_gram_with_degeneracy_and_rank_deficiency():
     assert np.abs(p_gpu - p_ref).max() < 1e-9
 
 
+@pytest.mark.parametrize("n,rank", [(40, 6), (64, 1), (256, 150)])
+def test_heev_full_rule_exact_null_space(n, rank):
+    # every eigenpair of a Gram matrix whose null space is exact (zero rows
+    # and columns): the whole eigenvector matrix must be unitary, as the
+    # truncated SVDs use it as a change of basis
+    rng = np.random.default_rng(n + rank)
+    b = rng.normal(size=(rank, rank // 2 + 1)) + 1j * rng.normal(size=(rank, rank // 2 + 1))
+    a = np.zeros((n, n), dtype=np.complex128)
+    a[:rank, :rank] = b @ b.conj().T
+    w, v, nv = _heev(n, a, rule=4)
+    assert nv == n
+    ref = np.sort(np.linalg.eigvalsh(a))[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() < 1e-13 * scale * n
+    assert np.abs(v.conj().T @ v - np.eye(n)).max() < 1e-12
+    assert np.abs(a @ v - v * w).max() < 1e-12 * scale
+
+
 def test_gates_match_oracle():
     wl = W.random_small_chain(3, 5)
     wl["lindblad"] = [[0.2 * SZ], [], [0.1 * (SX - 1j * SY) / 2], [], [0.3 * SX]]
