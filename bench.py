@@ -40,8 +40,53 @@ def parse():
     p.add_argument("--precision", default="fp64", choices=["fp64"])
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="time budget of the oracle CPU baseline (0 disables it)")
-    p.add_argument("--no-roofline", action="store_true", help="skip the per-kernel event timing pass")
+    p.add_argument("--kernel", default="eigensolver", choices=["eigensolver", "gemm", "none"],
+                   help="kernel class timed per launch with HIP events during the timed region "
+                        "(the dominant one) for the roofline object")
     return p.parse_args()
+
+
+KERNEL_CLASS = {"none": 0, "eigensolver": 1, "gemm": 2}
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6   # FP64 vector and FP64 dense matrix
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_sources(kind):
+    csrc = os.path.join(ROOT, "paper_2201_05529_amd", "csrc")
+    files = {"eigensolver": ["heev.h", "device_common.h"], "gemm": ["gemm.h", "bond_kernels.h", "device_common.h"]}
+    return [os.path.join(csrc, f) for f in files[kind]]
+
+
+def traffic_from_profiles(kind, launches_per_step):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(PROFILES, f"{kind}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in kernel_sources(kind):
+        with open(src, "rb") as g:
+            h.update(g.read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def roofline(kind, ms_total, launches, flops):
+    if kind == "none" or launches == 0 or ms_total <= 0.0:
+        return None
+    avg_s = ms_total * 1e-3 / launches
+    achieved = flops / launches / avg_s * 1e-12
+    bound = "alu" if kind == "eigensolver" else "mfma"
+    return {"bound": bound, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profiles(kind, launches),
+            "kernel": {"eigensolver": "heev_solve_kernel", "gemm": "k_bond_gemm"}[kind],
+            "launches": launches, "avg_launch_ms": ms_total / launches,
+            "alg_flops_per_launch": flops / launches}
 
 
 def library_baths(wl, n_steps):
@@ -130,6 +175,7 @@ def main():
     ch = make_chain(wl, baths)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
+    ch.kernel_timing(KERNEL_CLASS[args.kernel])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -139,6 +185,7 @@ def main():
             print(f"bench: step {k + 1}/{args.steps} {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ms_k, launches_k, flops_k = ch.kernel_timing_read()
     chi, xi = ch.bond_dims()
     value = n * args.steps / elapsed
     out = {
@@ -159,6 +206,9 @@ def main():
                    "precision": args.precision, "max_chi": int(chi.max()), "max_xi": int(xi.max()),
                    "trace": [tr.real, tr.imag], "ptmpo_build_s": t_ptmpo, "create_s": t_create},
     }
+    rl = roofline(args.kernel, ms_k, launches_k, flops_k)
+    if rl is not None:
+        out["roofline"] = rl
     ch.close()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

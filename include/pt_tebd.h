@@ -152,6 +152,21 @@ void pt_tebd_destroy(pt_tebd_t h);
  * Returns the first failing handle's status. */
 pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps);
 
+/* Measurement support (not part of the method).  pt_tebd_kernel_timing
+ * selects one kernel class (0 none, 1 the batched eigensolver's solve kernel,
+ * 2 the batched complex GEMM of the bond update) and resets the counters;
+ * while set, every launch of that class made by pt_tebd_step or
+ * pt_tebd_correlate on this handle is bracketed by HIP events on the
+ * handle's stream, and the kernels add their algorithmic flop counts
+ * (16 n^3 / 3 per n x n Hermitian tridiagonal reduction; 8 m n k per complex
+ * m x n x k product) to a device counter.  pt_tebd_kernel_timing_read
+ * synchronises and returns the summed event time (ms), the number of
+ * launches and the flop count since the last reset.  EINVAL for a bad
+ * class or null pointers. */
+pt_tebd_status pt_tebd_kernel_timing(pt_tebd_t h, int32_t kernel_class);
+pt_tebd_status pt_tebd_kernel_timing_read(pt_tebd_t h, double* total_ms, int64_t* launches,
+                                          double* alg_flops);
+
 /* Host helper (not on the hot path): PT-MPO of a Gaussian bosonic bath with
  * J(w) = 2 alpha w exp(-w/wc) (cutoff_kind 0) or 2 alpha w exp(-w^2/wc^2)
  * (cutoff_kind 1) at temperature T coupled through the d x d Hermitian

@@ -25,9 +25,10 @@ Two-site gate (Appendix A.2, Fig. tensor-network-contraction (c)-(h)):
 Truncation (Appendix A.2): the smallest rank with the 2-norm of the
 discarded singular values strictly below eps times the largest.  Readings:
 exact zeros are never kept, the rank is at least 1, the eps rule comes first
-and the chi_max cap second; if the cap splits a near-degenerate multiplet
-(neighbouring values closer than 1e-10 * sigma_1) the whole multiplet is
-dropped.
+and the chi_max cap second.  Neighbouring values within a relative gap of
+1e-6 form a multiplet, whose kept subspace is not determined by the values:
+an eps cut inside a multiplet moves to its end (the discarded tail only
+shrinks) and a cap that splits one drops it whole.
 
 PT absorption (Appendix A.2, Fig. tensor-network-contraction (i)-(j)):
   Gamma_n[a,s,e',b] <- sum_{e, s_in} P_k[e,e',s,s_in] Gamma_n[a,s_in,e,b].
@@ -53,7 +54,7 @@ from . import gates as gt
 from . import liouville as lv
 
 
-TIE_TOLERANCE = 1e-10
+TIE_TOLERANCE = 1e-6  # relative gap below which neighbouring singular values form a multiplet
 
 
 def truncation_rank(sv, eps, chi_max=None):
@@ -69,9 +70,14 @@ def truncation_rank(sv, eps, chi_max=None):
         if tail[c] < eps * sv[0]:
             rank = c
             break
+    # a cut inside a multiplet (consecutive singular values within a relative
+    # gap of TIE_TOLERANCE) leaves the kept subspace undetermined; the eps cut
+    # is moved to the multiplet's end, which only shrinks the discarded tail
+    while rank < n_pos and sv[rank - 1] - sv[rank] < TIE_TOLERANCE * sv[rank - 1]:
+        rank += 1
     if chi_max is not None and rank > chi_max:
         rank = chi_max
-        while rank > 1 and sv[rank - 1] - sv[rank] < TIE_TOLERANCE * sv[0]:
+        while rank > 1 and sv[rank - 1] - sv[rank] < TIE_TOLERANCE * sv[rank - 1]:
             rank -= 1
     return rank
 
@@ -255,10 +261,18 @@ class Engine:
         exp(log_scale), with v_n the vector contracted into site n."""
         hats = self.capped_sites(mps)
         left = np.ones(1, dtype=np.complex128)
+        log_acc = mps.log_scale
         for n, h in enumerate(hats):
             left = (left * mps.lams[n]) @ np.einsum("asz,s->az", h, site_vectors[n])
+            # keep the running vector at unit scale; its scale goes to the
+            # logarithm (the chain's log-scale and the tensors' own growth
+            # can each exceed the double range although their product does not)
+            nrm = np.abs(left).max()
+            if nrm > 0.0:
+                left = left / nrm
+                log_acc += np.log(nrm)
         left = left * mps.lams[-1]
-        return np.exp(mps.log_scale) * left.sum()
+        return np.exp(log_acc) * left.sum()
 
     def trace(self, mps=None):
         mps = self.mps if mps is None else mps

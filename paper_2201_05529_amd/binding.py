@@ -67,6 +67,8 @@ def lib():
         L.pt_tebd_restore.argtypes = [vp, vp, ctypes.c_size_t]
         L.pt_tebd_current_step.argtypes = [vp]
         L.pt_tebd_current_step.restype = i32
+        L.pt_tebd_kernel_timing.argtypes = [vp, i32]
+        L.pt_tebd_kernel_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
         L.pt_tebd_last_error.argtypes = [vp]
         L.pt_tebd_last_error.restype = ctypes.c_char_p
         L.pt_tebd_destroy.argtypes = [vp]
@@ -245,6 +247,18 @@ class Chain:
     def restore(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(lib().pt_tebd_restore(self.handle, ctypes.c_void_p(buf.ctypes.data), buf.size), "restore")
+
+    def kernel_timing(self, kernel_class):
+        """Select the kernel class timed per launch (0 none, 1 eigensolver
+        solve kernel, 2 bond-update GEMM) and reset its counters."""
+        self._check(lib().pt_tebd_kernel_timing(self.handle, int(kernel_class)), "kernel_timing")
+
+    def kernel_timing_read(self):
+        """(total event time in ms, launches, algorithmic flops) since the reset."""
+        ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._check(lib().pt_tebd_kernel_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(n),
+                                                     ctypes.byref(fl)), "kernel_timing_read")
+        return ms.value, n.value, fl.value
 
     def gate(self, bond):
         out = np.zeros(2 * 256)

@@ -268,12 +268,15 @@ __device__ inline bool gemm_args(const BondJob& J, int kind, int sub, GemmArgs& 
 }
 
 // grid (tiles_m, tiles_n, items * subs)
-__global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm(const BondJob* jobs, int kind, int subs) {
+// flops (may be null): accumulates 8 m n k per product (complex MAC = 8 flops)
+__global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm(const BondJob* jobs, int kind, int subs, double* flops) {
   __shared__ GemmSmem<double> sm;
   const int item = blockIdx.z / subs, sub = blockIdx.z - item * subs;
   GemmArgs g;
   if (!gemm_args(jobs[item], kind, sub, g)) return;
   if (g.m <= 0 || g.n <= 0) return;
+  if (flops && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    atomicAdd(flops, 8.0 * (double)g.m * g.n * g.k);
   gemm_tile<double>(g.A, g.lda, g.ca, g.B, g.ldb, g.cb, g.C, g.ldc, g.m, g.n, g.k,
                     mk<double>(g.alpha, 0.0), g.acc, blockIdx.x, blockIdx.y, sm);
 }
@@ -282,9 +285,9 @@ __global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm(const BondJob* jobs,
 // Truncation rule of Appendix A.2 on singular values s[0..n) given in
 // (eigenvalue) order: the smallest rank c whose discarded tail
 // sqrt(extra + sum_{i >= c} s_i^2) is strictly below eps * max(s); exact
-// zeros are never kept; rank >= 1; optional cap with the tie rule (a
-// multiplet split by the cap, neighbours within 1e-10 of the largest value,
-// is dropped whole).  Runs on one thread.
+// zeros are never kept; rank >= 1; an eps cut inside a multiplet
+// (neighbours within a relative gap of 1e-6) moves to its end; an optional
+// cap that splits a multiplet drops it whole.  Runs on one thread.
 __device__ inline int truncation_rank(const double* s, int n, double eps, double extra, int cap) {
   double smax = 0.0;
   int npos = 0;
@@ -301,9 +304,13 @@ __device__ inline int truncation_rank(const double* s, int n, double eps, double
     if (sqrt(tail) < thr) keep = i;
     else break;
   }
+  // an eps cut inside a multiplet (neighbours within a relative gap of
+  // 1e-6) moves to the multiplet's end, so the kept subspace is unique; the
+  // cap moves to the multiplet's start
+  while (keep < npos && fabs(s[keep - 1] - s[keep]) < 1e-6 * s[keep - 1]) ++keep;
   if (cap > 0 && keep > cap) {
     keep = cap;
-    while (keep > 1 && fabs(s[keep - 1] - s[keep]) < 1e-10 * smax) --keep;
+    while (keep > 1 && fabs(s[keep - 1] - s[keep]) < 1e-6 * s[keep - 1]) --keep;
   }
   return max(keep, 1);
 }

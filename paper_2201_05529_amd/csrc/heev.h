@@ -6,15 +6,16 @@
 //           (reflector H_j = I - tau_j v_j v_j^H, H_j^H x = beta e_1)
 //  stage 2  T + delta I = L D L^T with D > 0 (delta a few ulps of |T|, more
 //           if needed, so the factorisation exists)
-//  stage 3  every eigenvalue of L D L^T by multisection on qd negcounts, to
-//           high relative accuracy; then the selection rule (truncated-SVD
+//  stage 3  every eigenvalue of L D L^T: a shared grid of qd negative counts
+//           brackets all of them, then multisection to high relative
+//           accuracy (those at the rounding level keep the bracket); then
+//           the selection rule (truncated-SVD
 //           rule of Appendix A.2, or a numerical-rank rule) fixes how many
 //           leading eigenpairs are needed
 //  stage 4  their eigenvectors of T from twisted factorisations (one O(n)
 //           solve per vector); clusters of numerically equal eigenvalues
-//           get random starts, inverse iteration and Gram-Schmidt; the
-//           unresolved tail (eigenvalues at the rounding level) gets an
-//           orthonormal basis of the complement by Householder QR
+//           get random starts, inverse iteration and Gram-Schmidt against
+//           the cluster and its near neighbours
 //  stage 5  (separate kernel) back-transformation V = Q Z with the stored
 //           reflectors
 //  stage 6  (separate kernels) two passes of block classical Gram-Schmidt
@@ -96,12 +97,15 @@ __device__ inline int ldl_negcount(const double* d, const double* lld, int n, do
 }
 
 // ------------------------------------------------------------- stage 1..4
-__global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const HeevJob* jobs) {
+// flops (may be null): accumulates the algorithmic flop count of the
+// tridiagonal reduction, 16 n^3 / 3 per complex Hermitian matrix.
+__global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const HeevJob* jobs, double* flops) {
   constexpr int NT = HEEV_SOLVE_THREADS;
   const HeevJob& J = jobs[blockIdx.x];
   const int n = *J.n_ptr;
   if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
   const int tid = threadIdx.x;
+  if (flops && tid == 0) atomicAdd(flops, 16.0 / 3.0 * (double)n * n * n);
   __shared__ double buf[8192];     // stage 1: two v, w, partial sums; later: d, l, l d, l^2 d, mu, tau
   __shared__ double red[NT / 64];
   __shared__ double2 s_tau;
@@ -285,26 +289,61 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     }
     if (tnorm > 0.0 && tid == 0) atomicOr(J.status, 1);
   } else {
-    // -------- stage 3: eigenvalues of L D L^T by multisection, four
-    // threads per eigenvalue, geometric splits (relative accuracy)
+    // -------- stage 3: eigenvalues of L D L^T.  (a) one shared pass: every
+    // thread counts the eigenvalues below one point of a geometric grid over
+    // [1e-40 top, top], which brackets every eigenvalue to a factor 1.1;
+    // (b) each is refined by multisection with a group of te threads
+    // (te + 1 geometric subintervals per round) down to a few ulps
+    // (relative accuracy).
     const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
-    const int q = tid & 3;
-    for (int k0 = 0; k0 < n; k0 += NT / 4) {
-      const int k = k0 + (tid >> 2);
-      double lo = 1e-300 * (tnorm + delta), hi = 1.01 * (tnorm + delta) + 1e-300;
+    double* xg = buf + 6144;
+    int* cg = reinterpret_cast<int*>(buf + 7168);
+    const double top = 1.01 * (tnorm + delta) + 1e-300;
+    const double bot = fmax(1e-40 * top, 1e-300);
+    {
+      const double x = bot * exp((double)tid / (NT - 1) * log(top / bot));
+      xg[tid] = x;
+      cg[tid] = ldl_negcount(d, lld, n, x, pivmin);
+    }
+    __syncthreads();
+    const int knoise = 0;  // every eigenvalue is refined (relative accuracy keeps twisted vectors orthogonal)
+    auto bracket = [&](int k, double& lo, double& hi) {
+      int a = 0, b = NT;  // first grid point with more than k eigenvalues below
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (cg[mid] > k) b = mid;
+        else a = mid + 1;
+      }
+      hi = (a < NT) ? xg[a] : top;
+      lo = (a > 0) ? xg[a - 1] : 1e-300 * top;
+    };
+    for (int k = tid; k < knoise; k += NT) {
+      double lo, hi;
+      bracket(k, lo, hi);
+      const double m_k = fmin(0.5 * (lo + hi), 2.0 * delta);
+      mu[k] = m_k;
+      J.w[n - 1 - k] = m_k - delta;
+    }
+    const int nr = n - knoise;
+    int te = 1;
+    while (te < 64 && te * 2 * max(nr, 1) <= NT) te *= 2;
+    const int q = tid % te;
+    const int base = (tid & 63) & ~(te - 1);
+    for (int k0 = knoise; k0 < n; k0 += NT / te) {
+      const int k = k0 + tid / te;
+      double lo = 0.0, hi = 0.0;
       if (k < n) {
+        bracket(k, lo, hi);
+        const double f = (q + 1) / (double)(te + 1);
         for (int it = 0; it < 120; ++it) {
           if (hi - lo <= 4.4e-16 * hi) break;
           const bool geo = lo > 0.0 && hi > 4.0 * lo;
-          const double f = (q + 1) * 0.2;
           const double x = geo ? lo * exp(f * log(hi / lo)) : lo + f * (hi - lo);
           const int cnt = ldl_negcount(d, lld, n, x, pivmin);
-          // gather the four (x, cnt) pairs of this quad
           double nlo = lo, nhi = hi;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double xr = __shfl(x, ((threadIdx.x & 63) & ~3) + r, 64);
-            const int cr = __shfl(cnt, ((threadIdx.x & 63) & ~3) + r, 64);
+          for (int r = 0; r < te; ++r) {
+            const double xr = __shfl(x, base + r, 64);
+            const int cr = __shfl(cnt, base + r, 64);
             if (cr <= k) nlo = fmax(nlo, xr);
             else nhi = fmin(nhi, xr);
           }
@@ -344,11 +383,16 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
           if (sqrt(tail) < thr) nvec = i;   // keeping i values leaves tail(i)
           else break;
         }
+        // a cut inside a multiplet of singular values moves to its end
+        auto tie = [&](int k) {  // singular values k-1, k within a relative gap of 1e-6
+          const double a = sqrt(fmax(w[k - 1], 0.0)), b = sqrt(fmax(w[k], 0.0));
+          return a - b < 1e-6 * a;
+        };
+        while (nvec < npos && tie(nvec)) ++nvec;
         if (J.rule == RULE_CAP && J.cap > 0 && nvec > J.cap) {
           nvec = J.cap;
           // tie rule on singular values: drop a split multiplet
-          const double s0 = sqrt(lam0);
-          while (nvec > 1 && sqrt(fmax(w[nvec - 1], 0.0)) - sqrt(fmax(w[nvec], 0.0)) < 1e-10 * s0) --nvec;
+          while (nvec > 1 && tie(nvec)) --nvec;
         }
       }
     }
@@ -379,12 +423,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     return;
   }
   const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
-  // eigenvalues within the rounding level of the reduction (lambda <= delta,
-  // a few n eps |T|) are not resolved: their vectors are any orthonormal
-  // basis of the complement of the resolved ones (stage 4c).  They form a
-  // tail of the descending order.
-  int nres = 0;
-  while (nres < nvec && J.w[nres] > delta) ++nres;
+  const int nres = nvec;
   for (int k = tid; k < nres; k += NT) {
     const double m_k = mu[n - 1 - k];
     // top-down (stationary)
@@ -435,9 +474,9 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
 
   // -------- stage 4b: clusters of numerically equal eigenvalues (relative
   // gap below 1e-9).  Twisted vectors of equal mu coincide, so every member
-  // after the first restarts from a seeded random vector, takes two
-  // inverse-iteration solves with its own top-down factors, and is
-  // orthogonalised against the earlier members (one wave per cluster).
+  // after the first restarts from a seeded random vector, takes three
+  // inverse-iteration solves (pivoted elimination of T - lambda I), and is
+  // orthogonalised against the earlier members and near neighbours.
   {
     const double rgap = 1e-9;
     auto same = [&](int a, int b) {  // a, b descending-order indices
@@ -451,114 +490,103 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     // members: k with k > 0 and same(k - 1, k)
     for (int k = tid; k < nres; k += NT) {
       if (k == 0 || !same(k - 1, k)) continue;
-      const double m_k = mu[n - 1 - k];
-      // top-down factors of L D L^T - mu I with floored pivots: W(0) = l+,
-      // W(1) = D+
-      double s = -m_k;
+      // inverse iteration with T - lambda I factored by Gaussian elimination
+      // with partial pivoting (bounded growth; pivots floored at eps |T|)
+      const double lam = mu[n - 1 - k] - delta;
       for (int i = 0; i < n; ++i) {
-        double dp = d[i] + s;
-        if (fabs(dp) < pfloor) dp = dp < 0.0 ? -pfloor : pfloor;
-        W(1, i, k) = dp;
-        if (i + 1 < n) {
-          W(0, i, k) = ld[i] / dp;
-          s = lld[i] * (s / dp) - m_k;
+        W(0, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // sub-diagonal, then multipliers
+        W(1, i, k) = dd[i] - lam;                // diagonal of U
+        W(2, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // first super-diagonal of U
+        W(3, i, k) = 0.0;                        // second super-diagonal of U
+        W(4, i, k) = 0.0;                        // row swap at step i
+      }
+      for (int i = 0; i + 1 < n; ++i) {
+        const double di = W(1, i, k), li = W(0, i, k);
+        if (fabs(di) >= fabs(li)) {
+          W(0, i, k) = (di != 0.0) ? li / di : 0.0;
+          W(1, i + 1, k) -= W(0, i, k) * W(2, i, k);
+        } else {
+          const double f = di / li;
+          W(1, i, k) = li;
+          W(0, i, k) = f;
+          const double tmp = W(2, i, k);
+          W(2, i, k) = W(1, i + 1, k);
+          W(1, i + 1, k) = tmp - f * W(1, i + 1, k);
+          if (i + 2 < n) {
+            W(3, i, k) = W(2, i + 1, k);
+            W(2, i + 1, k) = -f * W(2, i + 1, k);
+          }
+          W(4, i, k) = 1.0;
         }
       }
-      for (int i = 0; i < n; ++i) Z(i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
-      for (int it = 0; it < 2; ++it) {
-        // (L+ D+ L+^T) y = z: forward with L+, divide by D+, backward with L+^T
-        for (int i = 0; i + 1 < n; ++i) Z(i + 1, k) -= W(0, i, k) * Z(i, k);
-        for (int i = 0; i < n; ++i) Z(i, k) /= W(1, i, k);
-        for (int i = n - 2; i >= 0; --i) Z(i, k) -= W(0, i, k) * Z(i + 1, k);
+      for (int i = 0; i < n; ++i)
+        if (fabs(W(1, i, k)) < pfloor) W(1, i, k) = W(1, i, k) >= 0.0 ? pfloor : -pfloor;
+      for (int i = 0; i < n; ++i) W(5, i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
+      for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i + 1 < n; ++i) {  // P, L
+          if (W(4, i, k) != 0.0) {
+            const double t = W(5, i, k);
+            W(5, i, k) = W(5, i + 1, k);
+            W(5, i + 1, k) = t;
+          }
+          W(5, i + 1, k) -= W(0, i, k) * W(5, i, k);
+        }
+        for (int i = n - 1; i >= 0; --i) {  // U
+          double acc = W(5, i, k);
+          if (i + 1 < n) acc -= W(2, i, k) * W(6, i + 1, k);
+          if (i + 2 < n) acc -= W(3, i, k) * W(6, i + 2, k);
+          W(6, i, k) = acc / W(1, i, k);
+        }
         double nr = 0.0;
-        for (int i = 0; i < n; ++i) nr += Z(i, k) * Z(i, k);
+        for (int i = 0; i < n; ++i) nr += W(6, i, k) * W(6, i, k);
         const double inv = (nr > 0.0 && nr < 1e300) ? 1.0 / sqrt(nr) : 0.0;
-        for (int i = 0; i < n; ++i) Z(i, k) *= inv;
+        for (int i = 0; i < n; ++i) W(5, i, k) = W(6, i, k) * inv;
       }
+      for (int i = 0; i < n; ++i) Z(i, k) = W(5, i, k);
     }
     __syncthreads();
+    // Gram-Schmidt (two passes, whole workgroup) of each member against the
+    // earlier members and against every vector whose eigenvalue lies within
+    // a relative gap of 1e-3 of the cluster (their twisted vectors may
+    // overlap the members' inverse-iteration vectors).
     const int lane = tid & 63, wid = tid >> 6;
-    // cluster starts, handed out round-robin to the waves
-    int cl = 0;
+    double* dots = buf + 6144;  // <= 1024 coefficients
+    auto near = [&](int a, int b) {
+      const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
+      return fabs(ma - mb) <= 1e-3 * fmax(fabs(ma), fabs(mb));
+    };
     for (int k = 0; k < nres; ++k) {
-      if (k > 0 && same(k - 1, k)) continue;  // not a start
+      if (k > 0 && same(k - 1, k)) continue;  // not a cluster start
       int e = k + 1;
       while (e < nres && same(e - 1, e)) ++e;
-      if (e - k >= 2 && (cl++ % (NT / 64)) == wid) {
-        for (int j = k + 1; j < e; ++j) {
-          for (int pass = 0; pass < 2; ++pass) {
-            for (int q2 = k; q2 < j; ++q2) {
-              double dot = 0.0;
-              for (int i = lane; i < n; i += 64) dot += Z(i, q2) * Z(i, j);
-              dot = warp_sum(dot);
-              for (int i = lane; i < n; i += 64) Z(i, j) -= dot * Z(i, q2);
-            }
-            double nr = 0.0;
-            for (int i = lane; i < n; i += 64) nr += Z(i, j) * Z(i, j);
-            nr = warp_sum(nr);
-            const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-            for (int i = lane; i < n; i += 64) Z(i, j) *= inv;
+      if (e - k < 2) continue;
+      int na = k, nb = e;
+      while (na > 0 && near(na - 1, k)) --na;
+      while (nb < nres && near(nb, k)) ++nb;
+      for (int j = k + 1; j < e; ++j) {
+        // reference vectors: [na, j) and [e, nb)
+        const int r1 = j - na, nref = r1 + (nb - e);
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int t = wid; t < nref; t += NT / 64) {
+            const int p = (t < r1) ? na + t : e + (t - r1);
+            double acc = 0.0;
+            for (int i = lane; i < n; i += 64) acc += Z(i, p) * Z(i, j);
+            acc = warp_sum(acc);
+            if (lane == 0) dots[t] = acc;
           }
+          __syncthreads();
+          double part = 0.0;
+          for (int i = tid; i < n; i += NT) {
+            double zi = Z(i, j);
+            for (int t = 0; t < nref; ++t) zi -= dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
+            Z(i, j) = zi;
+            part += zi * zi;
+          }
+          const double nr = block_sum(part, red);
+          const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+          for (int i = tid; i < n; i += NT) Z(i, j) *= inv;
+          __syncthreads();
         }
-      }
-    }
-  }
-  if (nres >= nvec) return;
-  __syncthreads();
-
-  // -------- stage 4c: unresolved tail.  Householder QR of a copy of the
-  // resolved vectors Z_h (n x h, orthonormal): H_{h-1} ... H_0 Z_h = [R; 0].
-  // Then Q = H_0 ... H_{h-1} and its columns h, h+1, ... are an orthonormal
-  // basis of the complement; column c = Q e_c is built by one thread
-  // applying the reflectors to e_c.  Reflector j is kept in W(3, i >= j, j),
-  // the copy of Z_h in W(4), tau_j in LDS.
-  {
-    double* rtau = buf + 5120;  // <= 1024 reflectors
-    const int h = nres;
-    for (int e = tid; e < n * h; e += NT) {
-      const int i = e / h, c = e - i * h;
-      W(4, i, c) = Z(i, c);
-    }
-    __syncthreads();
-    for (int j = 0; j < h; ++j) {
-      double part = 0.0;
-      for (int i = j + 1 + tid; i < n; i += NT) part += W(4, i, j) * W(4, i, j);
-      const double sig2 = block_sum(part, red);
-      if (tid == 0) {
-        const double alpha = W(4, j, j);
-        double tau = 0.0, beta = alpha;
-        if (sig2 > 0.0) {
-          const double nrm = sqrt(alpha * alpha + sig2);
-          beta = alpha >= 0.0 ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-        }
-        rtau[j] = tau;
-        s_beta = (tau != 0.0) ? 1.0 / (alpha - beta) : 0.0;
-      }
-      __syncthreads();
-      const double scl = s_beta;
-      const double tau = rtau[j];
-      for (int i = j + tid; i < n; i += NT) W(3, i, j) = (i == j) ? 1.0 : W(4, i, j) * scl;
-      __syncthreads();
-      if (tau != 0.0) {
-        for (int c = j + 1 + tid; c < h; c += NT) {  // one thread per column
-          double dot = 0.0;
-          for (int i = j; i < n; ++i) dot += W(3, i, j) * W(4, i, c);
-          dot *= tau;
-          for (int i = j; i < n; ++i) W(4, i, c) -= dot * W(3, i, j);
-        }
-      }
-      __syncthreads();
-    }
-    for (int c = h + tid; c < nvec; c += NT) {
-      for (int i = 0; i < n; ++i) Z(i, c) = (i == c) ? 1.0 : 0.0;
-      for (int j = h - 1; j >= 0; --j) {
-        const double tau = rtau[j];
-        if (tau == 0.0) continue;
-        double dot = 0.0;
-        for (int i = j; i < n; ++i) dot += W(3, i, j) * Z(i, c);
-        dot *= tau;
-        for (int i = j; i < n; ++i) Z(i, c) -= dot * W(3, i, j);
       }
     }
   }

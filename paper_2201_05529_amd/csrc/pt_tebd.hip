@@ -70,7 +70,7 @@ struct pt_tebd {
   unsigned long long seed = 0;
   int power_iters = 1;
   int oversample = 64;
-  int refine_levels = 3;
+  int refine_levels = 0;   // block refinement levels (PT_TEBD_REFINE_LEVELS)
   double refine_tau = 1e-4;
   int pt_steps = 0;           // shortest PT-MPO length
   Caps cap{};
@@ -96,6 +96,11 @@ struct pt_tebd {
   Sublayer sub_even, sub_odd;  // 1-based even bonds (0-based odd), 1-based odd bonds
   int step = 0;
   std::string err;
+  // per-launch timing of one kernel class (measurement support)
+  int timing_class = 0;
+  std::vector<hipEvent_t> events;  // start/end pairs, reused
+  size_t events_used = 0;
+  double* timing_flops = nullptr;  // device accumulator of algorithmic flops
 };
 
 namespace {
@@ -139,6 +144,7 @@ struct DevPtrs {
   double2* ops_out;
   double* ops_log;
   double2* site_op;
+  double* timing_flops;
   std::vector<BondJob> slots;          // scratch per slot (bond fields unset)
   std::vector<double2*> h_refl[2];
   std::vector<double*> h_tri[2], h_work[2], h_z[2];
@@ -165,6 +171,7 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     P.status[k] = bp.take<int>(1);
   }
   P.chains = bp.take<ChainDev>(2);
+  P.timing_flops = bp.take<double>(4);
   P.gates = bp.take<double2>((size_t)std::max(N - 1, 1) * 256);
   const int nbath = cfg->n_baths;
   P.baths = bp.take<BathDev>(std::max(nbath, 1));
@@ -340,15 +347,54 @@ int env_int(const char* name, int dflt) {
 }
 
 // ----------------------------------------------------------------- launch
+// ------------------------------------------------ per-launch kernel timing
+// When a handle has a timing class set, every launch of that class made
+// while the handle is being advanced is bracketed by a pair of events on the
+// handle's stream, and the kernels add their algorithmic flop counts to a
+// device accumulator.
+enum TimingClass : int { KT_NONE = 0, KT_EIGENSOLVER = 1, KT_BOND_GEMM = 2 };
+thread_local pt_tebd* t_timing = nullptr;
+
+struct TimingScope {
+  pt_tebd* prev;
+  explicit TimingScope(pt_tebd* h) : prev(t_timing) { t_timing = (h && h->timing_class) ? h : nullptr; }
+  ~TimingScope() { t_timing = prev; }
+};
+
+double* timed_flops(int cls) { return (t_timing && t_timing->timing_class == cls) ? t_timing->timing_flops : nullptr; }
+
+bool timed_begin(int cls, hipStream_t st) {
+  pt_tebd* h = t_timing;
+  if (!h || h->timing_class != cls) return false;
+  while (h->events.size() < h->events_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    h->events.push_back(e);
+  }
+  hipEventRecord(h->events[h->events_used], st);
+  return true;
+}
+
+void timed_end(bool began, hipStream_t st) {
+  if (!began) return;
+  pt_tebd* h = t_timing;
+  hipEventRecord(h->events[h->events_used + 1], st);
+  h->events_used += 2;
+}
+
 void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int subs, int m_cap, int n_cap) {
   dim3 grid((m_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (n_cap + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_items * subs);
-  ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs);
+  const bool t = timed_begin(KT_BOND_GEMM, st);
+  ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs, timed_flops(KT_BOND_GEMM));
+  timed_end(t, st);
 }
 
 int elem_blocks(long long n);
 
 void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
-  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs);
+  const bool t = timed_begin(KT_EIGENSOLVER, st);
+  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs, timed_flops(KT_EIGENSOLVER));
+  timed_end(t, st);
   dim3 grid((n_cap + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, n_jobs);
   const size_t shm = (size_t)n_cap * ptt::HEEV_BT_COLS * sizeof(double2);
   ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, shm, st>>>(jobs);
@@ -575,7 +621,9 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   } keep{h, err};
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
-  h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", 3));
+  // Gram matrices resolve singular values down to ~1e-8 of the largest; the
+  // block refinement is needed only when the truncation threshold is below
+  h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", cfg->svd_rel_cutoff < 1e-8 ? 3 : 0));
   h->cap = compute_caps(cfg, h->oversample);
   const Caps& c = h->cap;
   const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
@@ -706,6 +754,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   h->ops_out = P.ops_out;
   h->ops_log = P.ops_log;
   h->site_op = P.site_op;
+  h->timing_flops = P.timing_flops;
 
   // sublayer job tables
   for (int par = 0; par < 2; ++par) {
@@ -814,6 +863,7 @@ pt_tebd_status pt_tebd_step(pt_tebd_t h, int32_t n_steps) {
     h->err = "stepping past the end of a PT-MPO";
     return PT_TEBD_ERANGE;
   }
+  TimingScope timing(h);
   for (int i = 0; i < n_steps; ++i) {
     step_chain(h, 0, h->step + 1);
     ++h->step;
@@ -859,6 +909,7 @@ pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a
     h->err = "correlation runs past the end of a PT-MPO";
     return PT_TEBD_ERANGE;
   }
+  TimingScope timing(h);
   // trace of the main state at the insertion time
   const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
   double ov[8];
@@ -991,6 +1042,7 @@ const char* pt_tebd_last_error(pt_tebd_t h) {
 void pt_tebd_destroy(pt_tebd_t h) {
   if (!h) return;
   hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->events) hipEventDestroy(e);
   delete h;
 }
 
@@ -1000,6 +1052,35 @@ pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps) {
     const pt_tebd_status s = pt_tebd_step(hs[i], n_steps);
     if (s != PT_TEBD_OK) return s;
   }
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_kernel_timing(pt_tebd_t h, int32_t kernel_class) {
+  if (!h || kernel_class < KT_NONE || kernel_class > KT_BOND_GEMM) return PT_TEBD_EINVAL;
+  if (!check(hipStreamSynchronize(h->stream), h, "sync")) return PT_TEBD_EDEVICE;
+  h->timing_class = kernel_class;
+  h->events_used = 0;
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!check(hipMemcpy(h->timing_flops, zero, sizeof(zero), hipMemcpyHostToDevice), h, "timing reset"))
+    return PT_TEBD_EDEVICE;
+  return PT_TEBD_OK;
+}
+
+pt_tebd_status pt_tebd_kernel_timing_read(pt_tebd_t h, double* total_ms, int64_t* launches, double* alg_flops) {
+  if (!h || !total_ms || !launches || !alg_flops) return PT_TEBD_EINVAL;
+  if (!check(hipStreamSynchronize(h->stream), h, "sync")) return PT_TEBD_EDEVICE;
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < h->events_used; i += 2) {
+    float t = 0.0f;
+    if (!check(hipEventElapsedTime(&t, h->events[i], h->events[i + 1]), h, "event time")) return PT_TEBD_EDEVICE;
+    ms += t;
+  }
+  double fl[4];
+  if (!check(hipMemcpy(fl, h->timing_flops, sizeof(fl), hipMemcpyDeviceToHost), h, "timing read"))
+    return PT_TEBD_EDEVICE;
+  *total_ms = ms;
+  *launches = (int64_t)(h->events_used / 2);
+  *alg_flops = fl[0];
   return PT_TEBD_OK;
 }
 

@@ -114,6 +114,12 @@ def test_rotation_to_computational_basis():
     assert np.abs(acc[:, 0].reshape([4] * 4) - got_d).max() < 1e-13
 
 
+def oracle_problem_small(wl):
+    from oracle.build import problem_from_workload
+    prob, _ = problem_from_workload(wl, n_steps=2)
+    return prob
+
+
 def test_truncation_rule_examples():
     sv = np.array([1.0, 1e-3, 1e-8, 1e-9])
     assert truncation_rank(sv, 1e-7) == 2
@@ -123,3 +129,31 @@ def test_truncation_rule_examples():
     assert truncation_rank(np.array([1.0, 0.0, 0.0]), 0.0) == 1
     assert truncation_rank(np.array([1.0, 0.5, 0.5, 0.1]), 0.0, chi_max=2) == 1  # tie at the cap
     assert truncation_rank(np.array([1.0, 0.5, 0.4, 0.1]), 0.0, chi_max=2) == 2
+    # an eps cut inside a multiplet moves to the multiplet's end: the tail of
+    # [1, 1e-3, 9e-8, 9e-8] beyond rank 3 is 9e-8 < 1e-7 (beyond rank 2 it is
+    # 1.3e-7), but values 3 and 4 are equal, so both are kept
+    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8]), 1e-7) == 4
+    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 8e-8]), 1e-7) == 3
+    # ... and the cap still lowers to the multiplet's start
+    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8]), 1e-7, chi_max=3) == 2
+
+
+def test_read_out_survives_a_scale_beyond_the_double_range():
+    # the chain log-scale and the tensors may each leave the double range
+    # (the N = 21 workload reaches log-scale -714 by step 54) while the
+    # observable stays finite: shift scale between them and read out again
+    from oracle import pt_tebd
+    from paper_2201_05529_amd import workloads as W
+    wl = W.random_small_chain(9, 4, with_bath_sites=(1,), k_cut=2, eps=1e-10, xi_max=16)
+    prob = oracle_problem_small(wl)
+    eng = pt_tebd.Engine(prob)
+    eng.step(2)
+    ref = [eng.expectation(s, W.SZ) for s in range(4)]
+    tr = eng.trace()
+    shift = 300.0  # exp(4 * 300) overflows a double, exp(-4 * 300) underflows
+    eng.mps.log_scale -= 4 * shift
+    for n in range(4):
+        eng.mps.gammas[n] = eng.mps.gammas[n] * np.exp(shift)
+    got = [eng.expectation(s, W.SZ) for s in range(4)]
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14)
+    assert abs(eng.trace() - tr) < 1e-12
