@@ -128,79 +128,90 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   {
     double2* vbuf0 = reinterpret_cast<double2*>(buf);
     double2* vbuf1 = vbuf0 + 1024;
-    double2* sw = vbuf1 + 1024;   // pending w, then the new w
-    double2* part = sw + 1024;
+    double2* sy = vbuf1 + 1024;   // tau A v of the pending step (w = y - half v)
+    double2* part = sy + 1024;
     double2* vp = vbuf0;          // pending v (offset j at step j)
     double2* vc = vbuf1;          // current v
+    // per-wave partial sums, added in a fixed order (bit-reproducible)
+    __shared__ double s_sig[NT / 64];       // |x|^2 below the first entry
+    __shared__ double2 s_vhy[NT / 64];      // v^H y
+    __shared__ double2 s_alpha;
+    const int lane = tid & 63, wid = tid >> 6;
     bool pending = false;
+    double half = 0.0;            // of the pending step
     for (int j = 0; j + 1 < n; ++j) {
       const int m = n - j - 1, off = j + 1;
-      // (a) row j of the updated matrix: x = conj(row) below the diagonal
+      // (a) row j of the updated matrix; x = conj(row) below the diagonal
+      double p2 = 0.0;
       for (int i = tid; i < m; i += NT) {
         double2 val = A[(size_t)j * lda + off + i];
         if (pending) {
-          const double2 t1 = cmul<double>(sw[0], cconj<double>(vp[i + 1]));
-          const double2 t2 = cmul<double>(vp[0], cconj<double>(sw[i + 1]));
+          const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
+          const double2 wi = csub<double>(sy[i + 1], cscale<double>(vp[i + 1], half));
+          const double2 t1 = cmul<double>(w0, cconj<double>(vp[i + 1]));
+          const double2 t2 = cmul<double>(vp[0], cconj<double>(wi));
           val.x -= t1.x + t2.x;
           val.y -= t1.y + t2.y;
         }
-        vc[i] = cconj<double>(val);
+        const double2 x = cconj<double>(val);
+        vc[i] = x;
+        if (i == 0) s_alpha = x;
+        else p2 += cabs2<double>(x);
       }
+      p2 = warp_sum(p2);
+      if (lane == 0) s_sig[wid] = p2;
       if (tid == 0) {
         double a = A[(size_t)j * lda + j].x;
-        if (pending) a -= 2.0 * (sw[0].x * vp[0].x + sw[0].y * vp[0].y);
+        if (pending) {
+          const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
+          a -= 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
+        }
         dd[j] = a;
       }
       __syncthreads();
-      double p = 0.0;
-      for (int i = 1 + tid; i < m; i += NT) p += cabs2<double>(vc[i]);
-      const double sig2 = block_sum(p, red);
-      if (tid == 0) {
-        const double2 alpha = vc[0];
-        double2 tau = mk<double>(0.0, 0.0);
-        double beta = alpha.x;
-        if (!(sig2 == 0.0 && alpha.y == 0.0)) {
-          const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
-          beta = alpha.x >= 0.0 ? -nrm : nrm;
-          tau = mk<double>((beta - alpha.x) / beta, -alpha.y / beta);
-        }
-        s_tau = tau;
-        s_beta = beta;
-        taus[j] = tau;
-        ee[j] = beta;
+      // (b) reflector, computed redundantly by every thread
+      double sig2 = 0.0;
+      for (int q = 0; q < NT / 64; ++q) sig2 += s_sig[q];
+      const double2 alpha = s_alpha;
+      double2 tau = mk<double>(0.0, 0.0);
+      double beta = alpha.x;
+      if (!(sig2 == 0.0 && alpha.y == 0.0)) {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tau = mk<double>((beta - alpha.x) / beta, -alpha.y / beta);
       }
-      __syncthreads();
-      const double2 tau = s_tau;
-      const double beta = s_beta;
       const bool active = !(tau.x == 0.0 && tau.y == 0.0);
       double2 scal = mk<double>(0.0, 0.0);
       {
-        const double2 alpha = vc[0];
         const double2 den = mk<double>(alpha.x - beta, alpha.y);
         const double dn = den.x * den.x + den.y * den.y;
         if (active && dn > 0.0) scal = mk<double>(den.x / dn, -den.y / dn);
       }
-      __syncthreads();  // everyone has read vc[0]
+      if (tid == 0) {
+        taus[j] = tau;
+        ee[j] = beta;
+      }
       for (int i = tid; i < m; i += NT) {
-        double2 vi;
-        if (i == 0) vi = mk<double>(1.0, 0.0);
-        else vi = active ? cmul<double>(vc[i], scal) : mk<double>(0.0, 0.0);
+        const double2 vi = (i == 0) ? mk<double>(1.0, 0.0)
+                                    : (active ? cmul<double>(vc[i], scal) : mk<double>(0.0, 0.0));
         vc[i] = vi;
         J.refl[(size_t)j * nc + i] = vi;
       }
       __syncthreads();
-      // (b) fused pass: A22 -= pending update; part = conj(A22)^T v
+      // (c) fused pass: A22 -= pending update; part = conj(A22)^T v
       const int groups = max(1, NT / m);
       const int c = tid % m, g = tid / m;
       if (g < groups) {
         double2 acc = mk<double>(0.0, 0.0);
         if (pending) {
-          const double2 vpc = cconj<double>(vp[c + 1]), wpc = cconj<double>(sw[c + 1]);
+          const double2 wpc = cconj<double>(csub<double>(sy[c + 1], cscale<double>(vp[c + 1], half)));
+          const double2 vpc = cconj<double>(vp[c + 1]);
 #pragma unroll 4
           for (int r = g; r < m; r += groups) {
             double2* dst = A + (size_t)(off + r) * lda + off + c;
             double2 val = *dst;
-            const double2 t1 = cmul<double>(sw[r + 1], vpc);
+            const double2 wr = csub<double>(sy[r + 1], cscale<double>(vp[r + 1], half));
+            const double2 t1 = cmul<double>(wr, vpc);
             const double2 t2 = cmul<double>(vp[r + 1], wpc);
             val.x -= t1.x + t2.x;
             val.y -= t1.y + t2.y;
@@ -214,19 +225,23 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
         part[g * m + c] = acc;
       }
       __syncthreads();
-      // (c) w = tau y - 1/2 Re(conj(tau) v^H tau y) v becomes the pending update
+      // (d) y = tau A22 v (kept in sy); v^H y
       double2 pv = mk<double>(0.0, 0.0);
-      double2 y = mk<double>(0.0, 0.0);
       if (tid < m) {
+        double2 y = mk<double>(0.0, 0.0);
         for (int q = 0; q < groups; ++q) y = cadd<double>(y, part[q * m + tid]);
         y = cmul<double>(tau, y);
+        sy[tid] = y;
         cfmaconj<double>(pv, vc[tid], y);
       }
-      const double vhy_re = block_sum(pv.x, red);
-      const double vhy_im = block_sum(pv.y, red);
-      const double half = 0.5 * (tau.x * vhy_re + tau.y * vhy_im);
-      if (tid < m) sw[tid] = csub<double>(y, cscale<double>(vc[tid], half));
+      pv.x = warp_sum(pv.x);
+      pv.y = warp_sum(pv.y);
+      if (lane == 0) s_vhy[wid] = pv;
       __syncthreads();
+      // w = y - 1/2 Re(conj(tau) v^H y) v becomes the pending update
+      double2 vhy = mk<double>(0.0, 0.0);
+      for (int q = 0; q < NT / 64; ++q) vhy = cadd<double>(vhy, s_vhy[q]);
+      half = 0.5 * (tau.x * vhy.x + tau.y * vhy.y);
       double2* t = vp;
       vp = vc;
       vc = t;
@@ -234,7 +249,10 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     }
     if (tid == 0) {
       double a = A[(size_t)(n - 1) * lda + (n - 1)].x;
-      if (pending) a -= 2.0 * (sw[0].x * vp[0].x + sw[0].y * vp[0].y);
+      if (pending) {
+        const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
+        a -= 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
+      }
       dd[n - 1] = a;
       ee[n - 1] = 0.0;
     }

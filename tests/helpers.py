@@ -51,3 +51,31 @@ def run_both(wl, n_steps, ops, precision=0, form="tempo", oracle_mode="ch"):
         o.append([eng.expectation(s, op) for s, op in ops])
         ot.append(eng.trace())
     return np.array(g), np.array(o), np.array(gt), np.array(ot), ch, eng
+
+
+def oracle_sensitivity(prob, n_steps, ops, seeds=(1, 2), rel=1e-15):
+    """Per-step spread of the oracle's own observables under rounding-level
+    perturbations: after every step every entry of every site tensor is
+    multiplied by (1 + rel * complex normal), as a different floating-point
+    implementation of the same steps perturbs them.  Returns (base
+    [steps+1, n_ops], envelope [steps+1]) with envelope[k] = max over seeds
+    and ops of the deviation from the unperturbed run.  No other
+    floating-point implementation can be expected to reproduce the oracle
+    more closely than this."""
+    def run(seed):
+        eng = opt.Engine(prob)
+        rng = np.random.default_rng(seed)
+        out = []
+        for k in range(n_steps + 1):
+            if k:
+                eng.step(1)
+                if seed:
+                    for g in eng.mps.gammas:
+                        g *= 1.0 + rel * (rng.normal(size=g.shape) + 1j * rng.normal(size=g.shape))
+            out.append([eng.expectation(s, op) for s, op in ops])
+        return np.array(out)
+    base = run(0)
+    env = np.zeros(n_steps + 1)
+    for seed in seeds:
+        env = np.maximum(env, np.abs(run(seed) - base).max(axis=1))
+    return base, env
