@@ -64,6 +64,7 @@ enum Dim : int {
   D_K, D_KQ, D_KZ, D_GS,       // sketch width, basis widths, current Gram size
   D_CHI,                       // new bond dimension
   D_RF,                        // 1: randomised range finder active; 0: Q = identity (M <= sketch cap)
+  D_FB,                        // Gram size handed to the eigenvalue form of a second orthonormalisation pass (0: none)
   D_COUNT
 };
 

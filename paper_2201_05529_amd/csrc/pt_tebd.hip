@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "chain_kernels.h"
+#include "cholqr.h"
 #include "host_math.h"
 
 using ptt::BathDev;
@@ -45,6 +46,8 @@ struct Sublayer {
   HeevJob* heev_b = nullptr;     // device [2 n]
   HeevJob* heev_oy = nullptr;    // device [n]
   HeevJob* heev_oz = nullptr;    // device [n]
+  HeevJob* heev_oyb = nullptr;   // device [n]: eigenvalue form of the second pass (size dims[D_FB])
+  HeevJob* heev_ozb = nullptr;   // device [n]
   HeevJob* heev_rr = nullptr;    // device [n]
   ptt::RefineJob* ref_b = nullptr;  // device [2 n]: B_L, B_R
   ptt::RefineJob* ref_d = nullptr;  // device [n]
@@ -69,6 +72,7 @@ struct pt_tebd {
   pt_tebd_precision precision = PT_TEBD_FP64;
   unsigned long long seed = 0;
   int power_iters = 1;
+  bool cholqr = true;      // second orthonormalisation pass by Cholesky QR
   int oversample = 64;
   int refine_levels = 0;   // block refinement levels (PT_TEBD_REFINE_LEVELS)
   double refine_tau = 1e-4;
@@ -149,7 +153,7 @@ struct DevPtrs {
   std::vector<double2*> h_refl[2];
   std::vector<double*> h_tri[2], h_work[2], h_z[2];
   BondJob* jobs[2];
-  HeevJob *hb[2], *hoy[2], *hoz[2], *hrr[2], *hrb[2], *hrd[2];
+  HeevJob *hb[2], *hoy[2], *hoz[2], *hoyb[2], *hozb[2], *hrr[2], *hrb[2], *hrd[2];
   ptt::RefineJob *rb[2], *rd[2];
   std::vector<int*> blk;   // per slot: 3 x [2]
 };
@@ -249,6 +253,8 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     P.hb[par] = bp.take<HeevJob>(2 * n);
     P.hoy[par] = bp.take<HeevJob>(n);
     P.hoz[par] = bp.take<HeevJob>(n);
+    P.hoyb[par] = bp.take<HeevJob>(n);
+    P.hozb[par] = bp.take<HeevJob>(n);
     P.hrr[par] = bp.take<HeevJob>(n);
     P.hrb[par] = bp.take<HeevJob>(2 * n);
     P.hrd[par] = bp.take<HeevJob>(n);
@@ -455,13 +461,23 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   ptt::k_sketch_init<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J);
   launch_gemm(st, J, n, ptt::GK_SKETCH, 1, c.dn, c.kc);
   auto copy_dim = [&](int dst, int src) { ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, dst, src, 1); };
+  // second pass of an orthonormalisation: Cholesky QR, or the eigenvalue
+  // form for the jobs it declines (dims[D_FB] = 0 for the others)
+  auto second_pass = [&](const HeevJob* eig, const HeevJob* fallback) {
+    if (h->cholqr) {
+      ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J);
+      launch_heev(st, fallback, n, c.kc);
+    } else {
+      launch_heev(st, eig, n, c.kc);
+    }
+  };
   auto orth_y = [&]() {
     launch_gemm(st, J, n, ptt::GK_GRAM_YA, 1, c.kc, c.kc);
     launch_heev(st, S.heev_oy, n, c.kc);
     launch_gemm(st, J, n, ptt::GK_APPLY_YA, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KQ);
     launch_gemm(st, J, n, ptt::GK_GRAM_YB, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oy, n, c.kc);
+    second_pass(S.heev_oy, S.heev_oyb);
     launch_gemm(st, J, n, ptt::GK_APPLY_YB, 1, c.dn, c.kc);
   };
   orth_y();
@@ -473,7 +489,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     launch_gemm(st, J, n, ptt::GK_APPLY_ZA, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KZ);
     launch_gemm(st, J, n, ptt::GK_GRAM_ZB, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oz, n, c.kc);
+    second_pass(S.heev_oz, S.heev_ozb);
     launch_gemm(st, J, n, ptt::GK_APPLY_ZB, 1, c.dn, c.kc);
     launch_gemm(st, J, n, ptt::GK_D_Z, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KZ);
@@ -621,6 +637,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   } keep{h, err};
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
+  h->cholqr = env_int("PT_TEBD_CHOLQR", 1) != 0;
   // Gram matrices resolve singular values down to ~1e-8 of the largest; the
   // block refinement is needed only when the truncation threshold is below
   h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", cfg->svd_rel_cutoff < 1e-8 ? 3 : 0));
@@ -765,12 +782,15 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     S.heev_b = P.hb[par];
     S.heev_oy = P.hoy[par];
     S.heev_oz = P.hoz[par];
+    S.heev_oyb = P.hoyb[par];
+    S.heev_ozb = P.hozb[par];
     S.heev_rr = P.hrr[par];
     S.ref_b = P.rb[par];
     S.ref_d = P.rd[par];
     S.heev_ref_b = P.hrb[par];
     S.heev_ref_d = P.hrd[par];
     std::vector<HeevJob> hb2(2 * std::max(n, 1)), hoy(std::max(n, 1)), hoz(std::max(n, 1)), hrr(std::max(n, 1));
+    std::vector<HeevJob> hoyb(std::max(n, 1)), hozb(std::max(n, 1));
     std::vector<HeevJob> hrb(2 * std::max(n, 1)), hrd(std::max(n, 1));
     std::vector<ptt::RefineJob> rb(2 * std::max(n, 1)), rd(std::max(n, 1));
     for (int i = 0; i < n; ++i) {
@@ -798,6 +818,10 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
                 ptt::SCALE_INV_SQRT, st0);
       hoz[i] = hoy[i];
       hoz[i].nvec_out = J.dims + ptt::D_KZ;
+      hoyb[i] = hoy[i];
+      hoyb[i].n_ptr = J.dims + ptt::D_FB;
+      hozb[i] = hoz[i];
+      hozb[i].n_ptr = J.dims + ptt::D_FB;
       fill_heev(hrr[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
                 P.h_z[0][i], c.nh, J.dims + ptt::D_CHI, ptt::RULE_FULL, J.eps, cfg->chi_max, J.norms + 2, 0.0,
                 J.vk, c.kc, ptt::SCALE_NONE, st0);
@@ -836,6 +860,8 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
                 check(hipMemcpyAsync(S.heev_b, hb2.data(), 2 * n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_oy, hoy.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_oz, hoz.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_oyb, hoyb.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_ozb, hozb.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_rr, hrr.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_ref_b, hrb.data(), 2 * n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_ref_d, hrd.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
