@@ -75,7 +75,9 @@ struct BondJob {
   int bond;                // sites bond, bond+1
   const double2* gate;     // [16][16] site-major
   int chi_max;
-  int k_cap;               // sketch width cap
+  int k_cap;               // capacity of the sketch-side buffers (ld of omega, ya, yb, za, zb, gk, vk);
+                           // D is factorised exactly (Q = I) when M <= k_cap
+  int k_sketch;            // sketch width cap of the range finder (<= k_cap)
   double eps;
   unsigned long long seed;
   int nb_cap;              // capacity of B Gram sizes (4 chi_cap); ld of gl/gr/vl/vr
@@ -367,10 +369,10 @@ __global__ void k_apply_gate(const BondJob* jobs) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     D[D_M] = M;
     D[D_N] = N;
-    const int k = min(min(M, N), J.k_cap);
+    const int k = min(min(M, N), J.k_sketch);
     D[D_K] = k;
-    // M <= sketch cap: the identity is an orthonormal basis of the whole
-    // row space of D, so no range finder is needed (exact)
+    // M <= k_cap: the identity is an orthonormal basis of the whole row
+    // space of D, so no range finder is needed (exact)
     const int rf = (M > J.k_cap) ? 1 : 0;
     D[D_RF] = rf;
     D[D_GS] = rf ? k : 0;

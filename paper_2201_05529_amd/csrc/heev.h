@@ -15,7 +15,10 @@
 //  stage 4  their eigenvectors of T from twisted factorisations (one O(n)
 //           solve per vector); clusters of numerically equal eigenvalues
 //           get random starts, inverse iteration and Gram-Schmidt against
-//           the cluster and its near neighbours
+//           the cluster and its near neighbours; eigenvalues within the
+//           rounding level of zero (the numerical null space of a singular
+//           Gram matrix) form one such cluster, orthogonalised against all
+//           other vectors
 //  stage 5  (separate kernel) back-transformation V = Q Z with the stored
 //           reflectors
 //  stage 6  (separate kernels) two passes of block classical Gram-Schmidt
@@ -69,6 +72,7 @@ struct HeevJob {
   int ldv;
   int scale;         // HeevScale applied to column k with lambda_k
   int* status;       // sticky error word (bit 1: no convergence, bit 2: non-finite)
+  int noise_cluster; // 1: eigenvalues at the rounding level of zero form one cluster (stage 4b)
 };
 
 constexpr int HEEV_THREADS = 256;          // back-transformation kernel
@@ -495,11 +499,21 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   // after the first restarts from a seeded random vector, takes three
   // inverse-iteration solves (pivoted elimination of T - lambda I), and is
   // orthogonalised against the earlier members and near neighbours.
+  // Eigenvalues of T within delta of zero are rounding noise of a
+  // (numerically) singular matrix, not values known to any relative
+  // accuracy: they form one cluster whatever their relative gaps, every
+  // member of it (the first one too) is computed by inverse iteration, and
+  // each is orthogonalised against all other vectors.
   {
     const double rgap = 1e-9;
+    // |lambda| below the initial shift (8 n eps |T|) is rounding noise;
+    // mu = lambda + delta
+    const double noise = 8.0 * n * 2.2e-16 * tnorm;
+    const bool use_noise = J.noise_cluster != 0;
+    auto is_noise = [&](int a) { return use_noise && fabs(mu[n - 1 - a] - delta) <= noise; };
     auto same = [&](int a, int b) {  // a, b descending-order indices
       const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
-      return fabs(ma - mb) <= rgap * fmax(fabs(ma), fabs(mb));
+      return (is_noise(a) && is_noise(b)) || fabs(ma - mb) <= rgap * fmax(fabs(ma), fabs(mb));
     };
     // pivots of the (nearly) singular shifted matrix are floored at
     // eps |T|, as in inverse iteration: the solve then amplifies the
@@ -507,7 +521,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     const double pfloor = fmax(2.2e-16 * tnorm, pivmin);
     // members: k with k > 0 and same(k - 1, k)
     for (int k = tid; k < nres; k += NT) {
-      if (k == 0 || !same(k - 1, k)) continue;
+      if (!is_noise(k) && (k == 0 || !same(k - 1, k))) continue;
       // inverse iteration with T - lambda I factored by Gaussian elimination
       // with partial pivoting (bounded growth; pivots floored at eps |T|)
       const double lam = mu[n - 1 - k] - delta;
@@ -567,8 +581,8 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     // earlier members and against every vector whose eigenvalue lies within
     // a relative gap of 1e-3 of the cluster (their twisted vectors may
     // overlap the members' inverse-iteration vectors).
-    const int lane = tid & 63, wid = tid >> 6;
     double* dots = buf + 6144;  // <= 1024 coefficients
+    double* gsp = buf + 7168;   // NT partial sums
     auto near = [&](int a, int b) {
       const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
       return fabs(ma - mb) <= 1e-3 * fmax(fabs(ma), fabs(mb));
@@ -577,28 +591,63 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
       if (k > 0 && same(k - 1, k)) continue;  // not a cluster start
       int e = k + 1;
       while (e < nres && same(e - 1, e)) ++e;
-      if (e - k < 2) continue;
+      const bool nz = is_noise(e - 1);  // the cluster reaches the noise level
+      if (e - k < 2 && !nz) continue;
       int na = k, nb = e;
-      while (na > 0 && near(na - 1, k)) --na;
-      while (nb < nres && near(nb, k)) ++nb;
-      for (int j = k + 1; j < e; ++j) {
+      if (nz) {
+        na = 0;
+        nb = nres;
+      } else {
+        while (na > 0 && near(na - 1, k)) --na;
+        while (nb < nres && near(nb, k)) ++nb;
+      }
+      for (int j = is_noise(k) ? k : k + 1; j < e; ++j) {
         // reference vectors: [na, j) and [e, nb)
         const int r1 = j - na, nref = r1 + (nb - e);
         for (int pass = 0; pass < 2; ++pass) {
-          for (int t = wid; t < nref; t += NT / 64) {
-            const int p = (t < r1) ? na + t : e + (t - r1);
-            double acc = 0.0;
-            for (int i = lane; i < n; i += 64) acc += Z(i, p) * Z(i, j);
-            acc = warp_sum(acc);
-            if (lane == 0) dots[t] = acc;
+          // dots[t] = z_p(t) . z_j: 256 references at a time, the rows split
+          // over four thread groups (partial sums in LDS, added in a fixed
+          // order); rows of Z are contiguous in the vector index
+          const int rows_per = (n + 3) >> 2;
+          for (int c0 = 0; c0 < nref; c0 += 256) {
+            const int t = c0 + (tid & 255), g = tid >> 8;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            if (t < nref) {
+              const int p = (t < r1) ? na + t : e + (t - r1);
+              const int i0 = g * rows_per, i1 = min(n, i0 + rows_per);
+              int i = i0;
+              for (; i + 3 < i1; i += 4) {
+                a0 += Z(i, p) * Z(i, j);
+                a1 += Z(i + 1, p) * Z(i + 1, j);
+                a2 += Z(i + 2, p) * Z(i + 2, j);
+                a3 += Z(i + 3, p) * Z(i + 3, j);
+              }
+              for (; i < i1; ++i) a0 += Z(i, p) * Z(i, j);
+            }
+            gsp[tid] = (a0 + a1) + (a2 + a3);
+            __syncthreads();
+            if (tid < 256 && c0 + tid < nref) dots[c0 + tid] = ((gsp[tid] + gsp[256 + tid]) + gsp[512 + tid]) + gsp[768 + tid];
+            __syncthreads();
           }
-          __syncthreads();
+          // z_j -= sum_t dots[t] z_p(t): four lanes per row, combined by shuffles
           double part = 0.0;
-          for (int i = tid; i < n; i += NT) {
-            double zi = Z(i, j);
-            for (int t = 0; t < nref; ++t) zi -= dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
-            Z(i, j) = zi;
-            part += zi * zi;
+          const int q = tid & 3;
+          for (int i = tid >> 2; i < n; i += NT >> 2) {
+            double s0 = 0.0, s1 = 0.0;
+            int t = q;
+            for (; t + 4 < nref; t += 8) {
+              s0 += dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
+              s1 += dots[t + 4] * Z(i, (t + 4 < r1) ? na + t + 4 : e + (t + 4 - r1));
+            }
+            for (; t < nref; t += 4) s0 += dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
+            double sum = s0 + s1;
+            sum += __shfl_xor(sum, 1, 64);
+            sum += __shfl_xor(sum, 2, 64);
+            const double zi = Z(i, j) - sum;
+            if (q == 0) {
+              Z(i, j) = zi;
+              part += zi * zi;
+            }
           }
           const double nr = block_sum(part, red);
           const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;

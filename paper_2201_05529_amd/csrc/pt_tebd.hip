@@ -57,7 +57,7 @@ struct Sublayer {
 };
 
 struct Caps {
-  int n_sites, chi_cap, xi_cap, nb, dn, kc, nh, n_slots;
+  int n_sites, chi_cap, xi_cap, nb, dn, kc, ks, nh, n_slots;
   long long gam_cap;
 };
 
@@ -116,8 +116,12 @@ Caps compute_caps(const pt_tebd_config* cfg, int oversample) {
   c.xi_cap = std::max(1, cfg->xi_max);
   c.nb = 4 * c.chi_cap;
   c.dn = 4 * c.nb;
-  // the eigensolver holds one problem of size <= 1024 per workgroup
-  c.kc = std::min({c.dn, c.chi_cap + oversample, 1024});
+  // the eigensolver holds one problem of size <= 1024 per workgroup.  The
+  // range finder sketches chi_max + oversample columns; D with at most
+  // max(that, 4 chi_max) rows is factorised exactly instead (the Gram
+  // matrix of D is then no larger than those of B_L and B_R)
+  c.ks = std::min({c.dn, c.chi_cap + oversample, 1024});
+  c.kc = std::max(c.ks, std::min({c.dn, c.nb, 1024}));
   c.nh = std::max(c.nb, c.kc);
   c.n_slots = cfg->n_sites / 2;  // max(#even, #odd) bonds = floor(N/2)
   c.gam_cap = (long long)c.chi_cap * 4 * c.xi_cap * c.chi_cap;
@@ -601,6 +605,7 @@ void fill_heev(HeevJob& H, double2* a, int lda, int* n_ptr, double* w, double2* 
   H.a = a; H.lda = lda; H.n_ptr = n_ptr; H.w = w; H.refl = refl; H.tri = tri; H.work = work; H.z = z;
   H.n_cap = n_cap; H.nvec_out = nvec; H.rule = rule; H.eps = eps; H.cap = capv; H.extra_tail = extra;
   H.rank_tol = rank_tol; H.v = v; H.ldv = ldv; H.scale = scale; H.status = status;
+  H.noise_cluster = env_int("PT_TEBD_HEEV_NOISE", 1) != 0;
 }
 
 }  // namespace
@@ -638,9 +643,11 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
   h->cholqr = env_int("PT_TEBD_CHOLQR", 1) != 0;
-  // Gram matrices resolve singular values down to ~1e-8 of the largest; the
-  // block refinement is needed only when the truncation threshold is below
-  h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", cfg->svd_rel_cutoff < 1e-8 ? 3 : 0));
+  // Gram matrices resolve singular values down to ~1e-8 of the largest,
+  // which is where a truncation threshold eps ~ 1e-7 cuts: one level of
+  // block refinement resolves the block below 1e-4 of the largest relative
+  // to its own scale (down to ~1e-12); smaller thresholds take three
+  h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", cfg->svd_rel_cutoff < 1e-8 ? 3 : 1));
   h->cap = compute_caps(cfg, h->oversample);
   const Caps& c = h->cap;
   const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
@@ -800,6 +807,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
       J.gate = P.gates + (size_t)J.bond * 256;
       J.chi_max = cfg->chi_max;
       J.k_cap = c.kc;
+      J.k_sketch = c.ks;
       J.eps = cfg->svd_rel_cutoff;
       J.seed = ptt::splitmix64(cfg->seed ^ (0xA24BAED4963EE407ull * (unsigned long long)(J.bond + 1)));
       J.nb_cap = c.nb;

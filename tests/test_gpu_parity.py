@@ -111,6 +111,31 @@ def test_heev_full_rule_exact_null_space(n, rank):
     assert np.abs(a @ v - v * w).max() < 1e-12 * scale
 
 
+@pytest.mark.parametrize("n,rank,scale", [(224, 20, 1.0), (168, 16, 1.0), (64, 25, 1.0), (145, 8, 1e-40),
+                                          (256, 60, 1.0), (40, 39, 1e3)])
+def test_heev_full_rule_rounded_null_space(n, rank, scale):
+    # the Gram matrix of a rank-deficient block formed in floating point, as
+    # the two-site update builds it: the null space is rounding noise (of
+    # either sign, far below eps |lambda_0| in relative gaps), and the
+    # eigenvector matrix must still be unitary, since the small singular
+    # values are later re-resolved inside the span of those vectors
+    print(f"heev rounded null space n={n} rank={rank} scale={scale:g}", flush=True)
+    rng = np.random.default_rng(1000 + n + rank)
+    m = n + 17
+    u, _ = np.linalg.qr(rng.normal(size=(m, rank)) + 1j * rng.normal(size=(m, rank)))
+    v0, _ = np.linalg.qr(rng.normal(size=(n, rank)) + 1j * rng.normal(size=(n, rank)))
+    sv = np.sqrt(scale) * np.logspace(0, -12, rank)
+    b = (u * sv) @ v0.conj().T
+    a = b.conj().T @ b
+    a = 0.5 * (a + a.conj().T)
+    w, v, nv = _heev(n, a, rule=4)
+    assert nv == n
+    ref = np.sort(np.linalg.eigvalsh(a))[::-1]
+    assert np.abs(w - ref).max() < 1e-13 * scale * n
+    assert np.abs(v.conj().T @ v - np.eye(n)).max() < 1e-12
+    assert np.abs(a @ v - v * w).max() < 1e-12 * scale
+
+
 def test_gates_match_oracle():
     wl = W.random_small_chain(3, 5)
     wl["lindblad"] = [[0.2 * SZ], [], [0.1 * (SX - 1j * SY) / 2], [], [0.3 * SX]]
@@ -182,8 +207,7 @@ def test_xyz5_workload_and_correlation_match_oracle():
     errs = np.array(errs)
     print("  <sz> error by step (every 10th):", " ".join("%.1e" % e for e in errs[::10]), flush=True)
     print("  oracle rounding-level spread:     ", " ".join("%.1e" % e for e in env[::10]), flush=True)
-    assert errs[:11].max() < FP64_TOL, errs[:11]
-    assert errs.max() < LONG_TOL, errs
+    assert errs.max() < FP64_TOL, errs
 
 
 def test_xy21_workload_first_steps_match_oracle():
