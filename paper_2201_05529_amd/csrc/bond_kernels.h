@@ -377,6 +377,7 @@ __global__ void k_apply_gate(const BondJob* jobs) {
     D[D_RF] = rf;
     D[D_GS] = rf ? k : 0;
     if (!rf) D[D_KQ] = M;
+    D[D_FB] = 0;  // read by a launch that runs for every item
   }
   __shared__ double2 g[256];
   __shared__ double red[4];

@@ -71,7 +71,7 @@ struct HeevJob {
   double2* v;        // output eigenvectors, row-major n x nvec, leading dim ldv
   int ldv;
   int scale;         // HeevScale applied to column k with lambda_k
-  int* status;       // sticky error word (bit 1: no convergence, bit 2: non-finite)
+  int* status;       // sticky error word (bit 1: no convergence, bit 4: non-finite, bit 8: size above n_cap)
   int noise_cluster; // 1: eigenvalues at the rounding level of zero form one cluster (stage 4b)
 };
 
@@ -107,8 +107,12 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   constexpr int NT = HEEV_SOLVE_THREADS;
   const HeevJob& J = jobs[blockIdx.x];
   const int n = *J.n_ptr;
-  if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
   const int tid = threadIdx.x;
+  if (n > J.n_cap) {  // a size beyond the workspace: refuse (status bit 8)
+    if (tid == 0) atomicOr(J.status, 8);
+    return;
+  }
+  if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
   if (flops && tid == 0) atomicAdd(flops, 16.0 / 3.0 * (double)n * n * n);
   __shared__ double buf[8192];     // stage 1: two v, w, partial sums; later: d, l, l d, l^2 d, mu, tau
   __shared__ double red[NT / 64];
@@ -668,6 +672,7 @@ constexpr int HEEV_BT_COLS = 8;
 __global__ void __launch_bounds__(HEEV_THREADS) heev_backtransform_kernel(const HeevJob* jobs) {
   const HeevJob& J = jobs[blockIdx.y];
   const int n = *J.n_ptr;
+  if (n > J.n_cap) return;
   const int nvec = (n > 0) ? *J.nvec_out : 0;
   const int c0 = blockIdx.x * HEEV_BT_COLS;
   if (c0 >= nvec) return;
@@ -743,7 +748,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) heev_orth_gemm(const HeevJob* jo
   __shared__ GemmSmem<double> sm;
   const HeevJob& J = jobs[blockIdx.z];
   const int n = *J.n_ptr;
-  if (n <= 0) return;
+  if (n <= 0 || n > J.n_cap) return;
   const int nvec = *J.nvec_out;
   if (nvec < 2) return;
   if (kind == 0)
@@ -758,7 +763,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) heev_orth_gemm(const HeevJob* jo
 __global__ void heev_orth_mfix(const HeevJob* jobs) {
   const HeevJob& J = jobs[blockIdx.y];
   const int n = *J.n_ptr;
-  if (n <= 0) return;
+  if (n <= 0 || n > J.n_cap) return;
   const int nvec = *J.nvec_out;
   if (nvec < 2) return;
   double2* G = orth_g(J);
@@ -776,7 +781,7 @@ __global__ void heev_orth_mfix(const HeevJob* jobs) {
 __global__ void heev_orth_norm(const HeevJob* jobs, int from_t, int final_pass) {
   const HeevJob& J = jobs[blockIdx.y];
   const int n = *J.n_ptr;
-  if (n <= 0) return;
+  if (n <= 0 || n > J.n_cap) return;
   const int nvec = *J.nvec_out;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nvec) return;

@@ -539,7 +539,7 @@ pt_tebd_status device_status(pt_tebd* h, int which) {
              "status copy") ||
       !check(hipStreamSynchronize(h->stream), h, "stream sync"))
     return PT_TEBD_EDEVICE;
-  if (st & ptt::ST_RANGE) { h->err = "PT-MPO step or bond dimension mismatch on the device"; return PT_TEBD_ERANGE; }
+  if (st & ptt::ST_RANGE) { h->err = "PT-MPO step, bond dimension or work size out of range on the device"; return PT_TEBD_ERANGE; }
   if (st & (ptt::ST_NONFINITE | ptt::ST_ZERO)) { h->err = "non-finite value or zero norm during a bond update"; return PT_TEBD_ENUMERIC; }
   if (st & ptt::ST_EIG) { h->err = "eigensolver produced a non-finite value"; return PT_TEBD_ENUMERIC; }
   return PT_TEBD_OK;
