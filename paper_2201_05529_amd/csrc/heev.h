@@ -526,6 +526,12 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     // members: k with k > 0 and same(k - 1, k)
     for (int k = tid; k < nres; k += NT) {
       if (!is_noise(k) && (k == 0 || !same(k - 1, k))) continue;
+      if (is_noise(k)) {
+        // any vector of the null space will do: a seeded random start,
+        // projected onto the complement of the other vectors below
+        for (int i = 0; i < n; ++i) Z(i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
+        continue;
+      }
       // inverse iteration with T - lambda I factored by Gaussian elimination
       // with partial pivoting (bounded growth; pivots floored at eps |T|)
       const double lam = mu[n - 1 - k] - delta;
@@ -599,13 +605,43 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
       if (e - k < 2 && !nz) continue;
       int na = k, nb = e;
       if (nz) {
-        na = 0;
-        nb = nres;
+        // the whole cluster at once against every other vector (two block
+        // passes, coefficients C[t][c] in work array 7), then Gram-Schmidt
+        // inside the cluster only
+        const int m = e - k, r1 = k, nref = k + (nres - e);
+        double* C = J.work + (size_t)7 * nc * nc;
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = tid; q < nref * m; q += NT) {
+            const int t = q / m, c = q - t * m;
+            const int p = (t < r1) ? t : e + (t - r1);
+            double a0 = 0.0, a1 = 0.0;
+            int i = 0;
+            for (; i + 1 < n; i += 2) {
+              a0 += Z(i, p) * Z(i, k + c);
+              a1 += Z(i + 1, p) * Z(i + 1, k + c);
+            }
+            if (i < n) a0 += Z(i, p) * Z(i, k + c);
+            C[(size_t)t * nc + c] = a0 + a1;
+          }
+          __syncthreads();
+          for (int q = tid; q < n * m; q += NT) {
+            const int i = q / m, c = q - i * m;
+            double a0 = 0.0, a1 = 0.0;
+            int t = 0;
+            for (; t + 1 < nref; t += 2) {
+              a0 += Z(i, (t < r1) ? t : e + (t - r1)) * C[(size_t)t * nc + c];
+              a1 += Z(i, (t + 1 < r1) ? t + 1 : e + (t + 1 - r1)) * C[(size_t)(t + 1) * nc + c];
+            }
+            if (t < nref) a0 += Z(i, (t < r1) ? t : e + (t - r1)) * C[(size_t)t * nc + c];
+            Z(i, k + c) -= a0 + a1;
+          }
+          __syncthreads();
+        }
       } else {
         while (na > 0 && near(na - 1, k)) --na;
         while (nb < nres && near(nb, k)) ++nb;
       }
-      for (int j = is_noise(k) ? k : k + 1; j < e; ++j) {
+      for (int j = nz ? k : k + 1; j < e; ++j) {
         // reference vectors: [na, j) and [e, nb)
         const int r1 = j - na, nref = r1 + (nb - e);
         for (int pass = 0; pass < 2; ++pass) {

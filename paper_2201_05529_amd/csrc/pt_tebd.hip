@@ -71,7 +71,7 @@ struct pt_tebd {
   double eps = 0.0;
   pt_tebd_precision precision = PT_TEBD_FP64;
   unsigned long long seed = 0;
-  int power_iters = 1;
+  int power_iters = 2;
   bool cholqr = true;      // second orthonormalisation pass by Cholesky QR
   int oversample = 64;
   int refine_levels = 0;   // block refinement levels (PT_TEBD_REFINE_LEVELS)
@@ -109,6 +109,8 @@ struct pt_tebd {
 
 namespace {
 
+int env_int(const char* name, int dflt);
+
 Caps compute_caps(const pt_tebd_config* cfg, int oversample) {
   Caps c{};
   c.n_sites = cfg->n_sites;
@@ -121,7 +123,7 @@ Caps compute_caps(const pt_tebd_config* cfg, int oversample) {
   // max(that, 4 chi_max) rows is factorised exactly instead (the Gram
   // matrix of D is then no larger than those of B_L and B_R)
   c.ks = std::min({c.dn, c.chi_cap + oversample, 1024});
-  c.kc = std::max(c.ks, std::min({c.dn, c.nb, 1024}));
+  c.kc = std::max(c.ks, std::min({c.dn, env_int("PT_TEBD_EXACT_ROWS", c.nb), 1024}));
   c.nh = std::max(c.nb, c.kc);
   c.n_slots = cfg->n_sites / 2;  // max(#even, #odd) bonds = floor(N/2)
   c.gam_cap = (long long)c.chi_cap * 4 * c.xi_cap * c.chi_cap;
@@ -641,7 +643,9 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     ~KeepMessage() { if (h && !h->err.empty()) err = h->err; }
   } keep{h, err};
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
-  h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 1));
+  // two power iterations: with one, the leading subspace of D on the N = 21
+  // workload at its chi cap is off by ~1e-6 in the observables
+  h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 2));
   h->cholqr = env_int("PT_TEBD_CHOLQR", 1) != 0;
   // Gram matrices resolve singular values down to ~1e-8 of the largest,
   // which is where a truncation threshold eps ~ 1e-7 cuts: one level of
