@@ -457,16 +457,32 @@ __global__ void k_resid_copy(const BondJob* jobs) {
 
 // extra tail = ||D - Q Q^H D||_F^2 (0 when the sketch spans the range)
 // -> norms[2].  One block per item.
-__global__ void k_resid_norm(const BondJob* jobs) {
-  const BondJob& J = jobs[blockIdx.x];
+// partial sums of |residual|^2, one per block, into wk[blockIdx.x] (the
+// eigenvalue array is free between the orthonormalisations and the
+// Rayleigh-Ritz step).  grid (RESID_BLOCKS, items)
+constexpr int RESID_BLOCKS = 64;
+__global__ void k_resid_partial(const BondJob* jobs) {
+  const BondJob& J = jobs[blockIdx.y];
   const int* D = J.dims;
   const int M = D[D_M], N = D[D_N];
-  __shared__ double red[4];
+  __shared__ double red[16];
   double part = 0.0;
   if (D[D_K] < min(M, N))
-    for (long long idx = threadIdx.x; idx < (long long)M * N; idx += blockDim.x) part += cabs2<double>(J.p[idx]);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < (long long)M * N;
+         idx += (long long)gridDim.x * blockDim.x)
+      part += cabs2<double>(J.p[idx]);
   const double tot = block_sum(part, red);
-  if (threadIdx.x == 0) J.norms[2] = tot;
+  if (threadIdx.x == 0) J.wk[blockIdx.x] = tot;
+}
+
+// norms[2] = the partial sums added in block order.  One thread per item.
+__global__ void k_resid_norm(const BondJob* jobs, int n_items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondJob& J = jobs[i];
+  double tot = 0.0;
+  for (int b = 0; b < RESID_BLOCKS; ++b) tot += J.wk[b];
+  J.norms[2] = tot;
 }
 
 // New bond dimension from the (refined) singular values of D: eps rule with

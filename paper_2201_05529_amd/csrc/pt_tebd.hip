@@ -403,7 +403,9 @@ void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int
 
 int elem_blocks(long long n);
 
-void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
+// passes: block Gram-Schmidt passes of stage 6 (2), or 0 where the caller
+// re-orthonormalises the vectors anyway (then only the column scaling)
+void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap, int passes = 2) {
   const bool t = timed_begin(KT_EIGENSOLVER, st);
   ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs, timed_flops(KT_EIGENSOLVER));
   timed_end(t, st);
@@ -413,11 +415,15 @@ void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap) {
   const int tiles = (n_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM;
   const dim3 gg(tiles, tiles, n_jobs);
   const dim3 gn((n_cap + 255) / 256, n_jobs);
-  for (int pass = 0; pass < 2; ++pass) {
+  if (passes == 0) {
+    ptt::heev_orth_norm<<<gn, 256, 0, st>>>(jobs, 0, 1);
+    return;
+  }
+  for (int pass = 0; pass < passes; ++pass) {
     ptt::heev_orth_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs, 0);
     ptt::heev_orth_mfix<<<dim3(elem_blocks((long long)n_cap * n_cap), n_jobs), kThreads, 0, st>>>(jobs);
     ptt::heev_orth_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs, 1);
-    ptt::heev_orth_norm<<<gn, 256, 0, st>>>(jobs, 1, pass == 1);
+    ptt::heev_orth_norm<<<gn, 256, 0, st>>>(jobs, 1, pass == passes - 1);
   }
 }
 
@@ -427,7 +433,8 @@ int elem_blocks(long long n);
 void run_refine(pt_tebd* h, const ptt::RefineJob* R, const HeevJob* H, int n_jobs, int m_cap, int n_cap,
                 int nh) {
   hipStream_t st = h->stream;
-  ptt::k_ref_norms<<<n_jobs, kThreads, 0, st>>>(R);
+  const dim3 gnorm((nh + kThreads / 64 - 1) / (kThreads / 64), n_jobs);
+  ptt::k_ref_norms<<<gnorm, kThreads, 0, st>>>(R);
   for (int level = 0; level < h->refine_levels; ++level) {
     ptt::k_ref_select<<<(n_jobs + 63) / 64, 64, 0, st>>>(R, n_jobs, h->refine_tau, level);
     dim3 gg((nh + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (nh + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
@@ -438,7 +445,7 @@ void run_refine(pt_tebd* h, const ptt::RefineJob* R, const HeevJob* H, int n_job
     dim3 gv((nh + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (nh + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
     ptt::k_ref_gemm<<<gv, ptt::GEMM_THREADS, 0, st>>>(R, ptt::RK_ROTV);
     ptt::k_ref_copy<<<dim3(elem_blocks((long long)m_cap * n_cap), n_jobs), kThreads, 0, st>>>(R);
-    ptt::k_ref_norms<<<n_jobs, kThreads, 0, st>>>(R);
+    ptt::k_ref_norms<<<gnorm, kThreads, 0, st>>>(R);
   }
 }
 
@@ -479,7 +486,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   };
   auto orth_y = [&]() {
     launch_gemm(st, J, n, ptt::GK_GRAM_YA, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oy, n, c.kc);
+    launch_heev(st, S.heev_oy, n, c.kc, h->cholqr ? 0 : 2);
     launch_gemm(st, J, n, ptt::GK_APPLY_YA, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KQ);
     launch_gemm(st, J, n, ptt::GK_GRAM_YB, 1, c.kc, c.kc);
@@ -491,7 +498,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     launch_gemm(st, J, n, ptt::GK_DH_Q, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KQ);
     launch_gemm(st, J, n, ptt::GK_GRAM_ZA, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oz, n, c.kc);
+    launch_heev(st, S.heev_oz, n, c.kc, h->cholqr ? 0 : 2);
     launch_gemm(st, J, n, ptt::GK_APPLY_ZA, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KZ);
     launch_gemm(st, J, n, ptt::GK_GRAM_ZB, 1, c.kc, c.kc);
@@ -504,7 +511,8 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   launch_gemm(st, J, n, ptt::GK_QH_D, 1, c.kc, c.dn);
   ptt::k_resid_copy<<<dim3(elem_blocks((long long)c.dn * c.dn), n), kThreads, 0, st>>>(J);
   launch_gemm(st, J, n, ptt::GK_RESID, 1, c.dn, c.dn);
-  ptt::k_resid_norm<<<n, kThreads, 0, st>>>(J);
+  ptt::k_resid_partial<<<dim3(ptt::RESID_BLOCKS, n), kThreads, 0, st>>>(J);
+  ptt::k_resid_norm<<<(n + 63) / 64, 64, 0, st>>>(J, n);
   ptt::k_copy_dim<<<(n + 63) / 64, 64, 0, st>>>(J, n, ptt::D_GS, ptt::D_KQ, 0);
   launch_gemm(st, J, n, ptt::GK_GRAM_BM, 1, c.kc, c.kc);
   launch_heev(st, S.heev_rr, n, c.kc);

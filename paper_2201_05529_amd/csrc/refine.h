@@ -41,13 +41,14 @@ __device__ inline int ref_cols(const RefineJob& R) { return R.side_ptr ? (*R.sid
 __device__ inline int ref_len(const RefineJob& R) { return ref_cols(R) ? *R.len_cols : *R.len_rows; }
 __device__ inline int ref_ldp(const RefineJob& R) { return R.ldp_ptr ? *R.ldp_ptr : R.ldp; }
 
-// norms of every vector; one block per job
+// norms of every vector, one wave per vector.  grid (blocks, jobs)
 __global__ void k_ref_norms(const RefineJob* jobs) {
-  const RefineJob& R = jobs[blockIdx.x];
+  const RefineJob& R = jobs[blockIdx.y];
   const int n = *R.n_ptr, len = ref_len(R), ldp = ref_ldp(R), cols = ref_cols(R);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int wid = blockIdx.x * nw + (threadIdx.x >> 6), stride = gridDim.x * nw;
   const long long si = cols ? 1 : ldp, se = cols ? ldp : 1;
-  for (int i = wid; i < n; i += nw) {
+  for (int i = wid; i < n; i += stride) {
     double acc = 0.0;
     for (int e = lane; e < len; e += 64) acc += cabs2<double>(R.P[(long long)i * si + (long long)e * se]);
     acc = warp_sum(acc);
