@@ -10,7 +10,8 @@
 
 namespace ptt {
 
-constexpr int GEMM_BM = 64, GEMM_BN = 64, GEMM_BK = 8, GEMM_THREADS = 256;
+constexpr int GEMM_BM = 64, GEMM_BN = 64, GEMM_BK = 16, GEMM_THREADS = 256;
+constexpr int GEMM_LD = GEMM_BM * GEMM_BK / GEMM_THREADS;  // elements of A (and of B) each thread loads per k-step
 
 template <typename T>
 struct GemmSmem {
@@ -18,6 +19,9 @@ struct GemmSmem {
   cx<T> b[GEMM_BK][GEMM_BN + 1];
 };
 
+// The next k-slice is loaded into registers while the current one is
+// multiplied out of LDS, so global latency overlaps the arithmetic; two
+// barriers per slice of GEMM_BK.
 template <typename T>
 __device__ inline void gemm_tile(const cx<T>* __restrict__ A, int lda, bool conjA,
                                  const cx<T>* __restrict__ B, int ldb, bool conjB,
@@ -34,32 +38,49 @@ __device__ inline void gemm_tile(const cx<T>* __restrict__ A, int lda, bool conj
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = mk<T>(0, 0);
 
+  // element e = tid + t * GEMM_THREADS of a slice; each operand is read
+  // along its row-major fast index (coalesced)
+  int ar[GEMM_LD], ap[GEMM_LD], bc[GEMM_LD], bp[GEMM_LD];
+#pragma unroll
+  for (int t = 0; t < GEMM_LD; ++t) {
+    const int e = tid + t * GEMM_THREADS;
+    ar[t] = conjA ? (e & (GEMM_BM - 1)) : (e / GEMM_BK);
+    ap[t] = conjA ? (e / GEMM_BM) : (e & (GEMM_BK - 1));
+    bc[t] = conjB ? (e / GEMM_BK) : (e & (GEMM_BN - 1));
+    bp[t] = conjB ? (e & (GEMM_BK - 1)) : (e / GEMM_BN);
+  }
+  cx<T> ra[GEMM_LD], rb[GEMM_LD];
+#pragma unroll
+  for (int t = 0; t < GEMM_LD; ++t) {
+    const int gr = row0 + ar[t], gp = ap[t];
+    ra[t] = mk<T>(0, 0);
+    if (gr < m && gp < k) ra[t] = conjA ? cconj<T>(A[(size_t)gp * lda + gr]) : A[(size_t)gr * lda + gp];
+    const int gc = col0 + bc[t], gq = bp[t];
+    rb[t] = mk<T>(0, 0);
+    if (gc < n && gq < k) rb[t] = conjB ? cconj<T>(B[(size_t)gc * ldb + gq]) : B[(size_t)gq * ldb + gc];
+  }
   for (int k0 = 0; k0 < k; k0 += GEMM_BK) {
-    // A tile: BM x BK elements, 2 per thread
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int e = tid + t * GEMM_THREADS;
-      int r, p;
-      if (conjA) { r = e & 63; p = e >> 6; }   // coalesced along r
-      else { p = e & 7; r = e >> 3; }          // coalesced along p
-      const int gr = row0 + r, gp = k0 + p;
-      cx<T> v = mk<T>(0, 0);
-      if (gr < m && gp < k) v = conjA ? cconj<T>(A[(size_t)gp * lda + gr]) : A[(size_t)gr * lda + gp];
-      sm.a[p][r] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int e = tid + t * GEMM_THREADS;
-      int c, p;
-      if (conjB) { p = e & 7; c = e >> 3; }
-      else { c = e & 63; p = e >> 6; }
-      const int gc = col0 + c, gp = k0 + p;
-      cx<T> v = mk<T>(0, 0);
-      if (gc < n && gp < k) v = conjB ? cconj<T>(B[(size_t)gc * ldb + gp]) : B[(size_t)gp * ldb + gc];
-      sm.b[p][c] = v;
+    for (int t = 0; t < GEMM_LD; ++t) {
+      sm.a[ap[t]][ar[t]] = ra[t];
+      sm.b[bp[t]][bc[t]] = rb[t];
     }
     __syncthreads();
+    const int k1 = k0 + GEMM_BK;
+    if (k1 < k) {
 #pragma unroll
+      for (int t = 0; t < GEMM_LD; ++t) {
+        const int gr = row0 + ar[t], gp = k1 + ap[t];
+        ra[t] = mk<T>(0, 0);
+        if (gr < m && gp < k) ra[t] = conjA ? cconj<T>(A[(size_t)gp * lda + gr]) : A[(size_t)gr * lda + gp];
+        const int gc = col0 + bc[t], gq = k1 + bp[t];
+        rb[t] = mk<T>(0, 0);
+        if (gc < n && gq < k) rb[t] = conjB ? cconj<T>(B[(size_t)gc * ldb + gq]) : B[(size_t)gq * ldb + gc];
+      }
+    }
+    // two k-steps per iteration: full unrolling hoists every LDS load and
+    // spills; two keep the accumulators and operands in registers
+#pragma unroll 2
     for (int p = 0; p < GEMM_BK; ++p) {
       cx<T> av[4], bv[4];
 #pragma unroll
