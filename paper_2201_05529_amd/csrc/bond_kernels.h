@@ -393,7 +393,9 @@ __global__ void k_apply_gate(const BondJob* jobs) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int t = 0; t < 4; ++t) in[s * 4 + t] = J.p[(long long)(li * 4 + s) * N + t * r + ri];
-#pragma unroll
+    // one output row of the gate at a time: unrolling all four hoists the
+    // 256 gate entries out of LDS into registers and spills
+#pragma unroll 1
     for (int so = 0; so < 4; ++so)
 #pragma unroll
       for (int to = 0; to < 4; ++to) {

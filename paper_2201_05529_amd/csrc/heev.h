@@ -610,30 +610,66 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
         // inside the cluster only
         const int m = e - k, r1 = k, nref = k + (nres - e);
         double* C = J.work + (size_t)7 * nc * nc;
+        // 4 x 4 register blocks: eight loads feed sixteen multiply-adds
+        const int tb = (nref + 3) >> 2, cb = (m + 3) >> 2, ib = (n + 3) >> 2;
         for (int pass = 0; pass < 2; ++pass) {
-          for (int q = tid; q < nref * m; q += NT) {
-            const int t = q / m, c = q - t * m;
-            const int p = (t < r1) ? t : e + (t - r1);
-            double a0 = 0.0, a1 = 0.0;
-            int i = 0;
-            for (; i + 1 < n; i += 2) {
-              a0 += Z(i, p) * Z(i, k + c);
-              a1 += Z(i + 1, p) * Z(i + 1, k + c);
+          // C[t][c] = z_p(t) . z_(k+c)
+          for (int q = tid; q < tb * cb; q += NT) {
+            const int t0 = (q / cb) * 4, c0 = (q % cb) * 4;
+            int pt[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int t = min(t0 + u, nref - 1);
+              pt[u] = (t < r1) ? t : e + (t - r1);
             }
-            if (i < n) a0 += Z(i, p) * Z(i, k + c);
-            C[(size_t)t * nc + c] = a0 + a1;
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            for (int i = 0; i < n; ++i) {
+              double zp[4], zm[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) zp[u] = Z(i, pt[u]);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) zm[v] = Z(i, k + min(c0 + v, m - 1));
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(zp[u], zm[v], acc[u][v]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                if (t0 + u < nref && c0 + v < m) C[(size_t)(t0 + u) * nc + c0 + v] = acc[u][v];
           }
           __syncthreads();
-          for (int q = tid; q < n * m; q += NT) {
-            const int i = q / m, c = q - i * m;
-            double a0 = 0.0, a1 = 0.0;
-            int t = 0;
-            for (; t + 1 < nref; t += 2) {
-              a0 += Z(i, (t < r1) ? t : e + (t - r1)) * C[(size_t)t * nc + c];
-              a1 += Z(i, (t + 1 < r1) ? t + 1 : e + (t + 1 - r1)) * C[(size_t)(t + 1) * nc + c];
+          // z_(k+c) -= sum_t z_p(t) C[t][c]
+          for (int q = tid; q < ib * cb; q += NT) {
+            const int i0 = (q / cb) * 4, c0 = (q % cb) * 4;
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            for (int t = 0; t < nref; ++t) {
+              const int p = (t < r1) ? t : e + (t - r1);
+              double zr[4], cv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) zr[u] = Z(min(i0 + u, n - 1), p);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) cv[v] = C[(size_t)t * nc + min(c0 + v, m - 1)];
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(zr[u], cv[v], acc[u][v]);
             }
-            if (t < nref) a0 += Z(i, (t < r1) ? t : e + (t - r1)) * C[(size_t)t * nc + c];
-            Z(i, k + c) -= a0 + a1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                if (i0 + u < n && c0 + v < m) Z(i0 + u, k + c0 + v) -= acc[u][v];
           }
           __syncthreads();
         }
