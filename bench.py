@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--precision", default="fp64", choices=["fp64"])
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="time budget of the oracle CPU baseline (0 disables it)")
+    p.add_argument("--chains", type=int, default=1,
+                   help="independent copies of the workload, each on a stream of its own (value = their total)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="before the workload, run one element-wise copy kernel that reads and writes MIB MiB "
                         "(the reference for hardware byte counters)")
@@ -105,10 +107,10 @@ def library_baths(wl, n_steps):
     return out
 
 
-def make_chain(wl, baths):
+def make_chain(wl, baths, stream=None):
     from paper_2201_05529_amd import binding as B
     return B.Chain(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths, chi_max=wl["chi_max"],
-                   xi_max=wl["xi_max"], eps=wl["eps"], lindblad=wl.get("lindblad"))
+                   xi_max=wl["xi_max"], eps=wl["eps"], lindblad=wl.get("lindblad"), stream=stream)
 
 
 def cpu_baseline(wl, seconds):
@@ -182,7 +184,12 @@ def main():
         del ch
 
     t0 = time.perf_counter()
-    ch = make_chain(wl, baths)
+    n_chains = max(1, args.chains)
+    # one chain on the current stream; further copies on streams of their
+    # own (default priority), so their launches overlap on the device
+    streams = [None] + [torch.cuda.Stream() for _ in range(n_chains - 1)]
+    chains = [make_chain(wl, baths, stream=st) for st in streams]
+    ch = chains[0]
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     ch.kernel_timing(KERNEL_CLASS[args.kernel])
@@ -190,8 +197,10 @@ def main():
     t0 = time.perf_counter()
     peak_chi, peak_xi = 0, 0
     for k in range(args.steps):
-        ch.step(1)
-        vals, tr = ch.observe(sites, ops)
+        for c in chains:
+            c.step(1)
+        for c in chains:
+            vals, tr = c.observe(sites, ops)
         chi, xi = ch.bond_dims()
         peak_chi, peak_xi = max(peak_chi, int(chi.max())), max(peak_xi, int(xi.max()))
         if (k + 1) % 10 == 0:
@@ -199,7 +208,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_k, launches_k, flops_k = ch.kernel_timing_read()
-    value = n * args.steps / elapsed
+    value = n_chains * n * args.steps / elapsed
     out = {
         "metric": METRIC,
         "value": value,
@@ -214,14 +223,16 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={n} XY chain, a bath on every site, chi<={wl['chi_max']}, "
-                               f"xi<={wl['xi_max']}, dt={wl['dt']}, steps 1..{args.steps}, FP64 plain",
+                               f"xi<={wl['xi_max']}, dt={wl['dt']}, steps 1..{args.steps}, FP64 plain"
+                               + (f", {n_chains} independent copies on {n_chains} streams" if n_chains > 1 else ""),
                    "precision": args.precision, "peak_chi": peak_chi, "peak_xi": peak_xi,
                    "trace": [tr.real, tr.imag], "ptmpo_build_s": t_ptmpo, "create_s": t_create},
     }
     rl = roofline(args.kernel, ms_k, launches_k, flops_k)
     if rl is not None:
         out["roofline"] = rl
-    ch.close()
+    for c in chains:
+        c.close()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
