@@ -65,6 +65,8 @@ enum Dim : int {
   D_CHI,                       // new bond dimension
   D_RF,                        // 1: randomised range finder active; 0: Q = identity (M <= sketch cap)
   D_FB,                        // Gram size handed to the eigenvalue form of a second orthonormalisation pass (0: none)
+  D_GS0, D_K1, D_GS2, D_K2,    // deflation: sketch width at entry, level-1 rank, residual Gram size (0: none), level-2 rank
+  D_G2S, D_FB2,                // level-2 second-pass Gram size, its eigenvalue-form size (0: none)
   D_COUNT
 };
 
@@ -84,7 +86,8 @@ struct BondJob {
   int dn_cap;              // capacity of M, N (4 nb_cap)
   int ldr;                 // leading dim of pr (max(xi_cap chi_cap, nb_cap))
   int* dims;               // [D_COUNT]
-  double* norms;           // [4]: ||D||_F^2, ||Q^H D||_F^2, extra tail, spare
+  double* norms;           // [8]: ||D||_F^2, ||Q^H D||_F^2, extra tail, log-scale term,
+                           //      largest Gram eigenvalue of the basis being orthonormalised
   double2 *bl, *br, *gl, *gr, *vl, *vr, *x, *y, *p, *d;
   double *wl, *wr, *wk;
   double *sl, *sr, *sk;    // singular values (norms) for B_L, B_R, D
@@ -152,6 +155,22 @@ enum GemmKind : int {
   GK_UD,           // ud = ya vk                       (M x CHI)
   GK_NEWL,         // tg = pl (S^-1 ud') (side 0) | U_L ud' (side 1)      (rl x 4 chi)
   GK_NEWR,         // tg = (vdh' S^-1) pr (side 0) | vdh' V_R^H (side 1) (4 chi x cr)
+  // deflated orthonormalisation of the range finder's bases.  Basis X
+  // (rows R) with scratch S and T: Y side X = ya, S = za, T = yb, R = M; Z
+  // side X = za, S = ya, T = zb, R = N.  The kind is GK_DF + 2 op + side.
+  GK_DF,
+};
+enum DeflOp : int {
+  DF_APPLY1 = 0,   // S = T vk                         (R x Kb, k = GS)     Kb = KQ | KZ
+  DF_C,            // gk = S^H X                       (K1 x GS2, k = R)
+  DF_R,            // X -= S gk                        (R x GS2, k = K1)
+  DF_GRAM2,        // gk = X^H X                       (GS2 x GS2, k = R)
+  DF_APPLY2,       // T = X vk                         (R x K2, k = GS2)
+  DF_C2,           // gk = S^H T                       (K1 x K2, k = R)
+  DF_R2,           // T -= S gk                        (R x K2, k = K1)
+  DF_GRAM2B,       // gk = T^H T                       (G2S x G2S, k = R)
+  DF_APPLY2B,      // S[:, K1:] = T vk                 (R x K2, k = G2S)
+  DF_OPS
 };
 
 struct GemmArgs {
@@ -176,6 +195,30 @@ __device__ inline bool gemm_args(const BondJob& J, int kind, int sub, GemmArgs& 
   // the sketch / orthonormalisation / power-iteration products run only
   // when the range finder is active
   if (kind >= GK_SKETCH && kind <= GK_D_Z && D[D_RF] == 0) return false;
+  if (kind >= GK_DF) {
+    if (D[D_RF] == 0) return false;
+    const int op = (kind - GK_DF) >> 1, side = (kind - GK_DF) & 1;
+    double2* X = side ? J.za : J.ya;
+    double2* S = side ? J.ya : J.za;
+    double2* T = side ? J.zb : J.yb;
+    const int R = side ? D[D_N] : D[D_M], kb = side ? D[D_KZ] : D[D_KQ];
+    const int k1 = D[D_K1], gs2 = D[D_GS2], k2 = D[D_K2];
+    // level 2 runs only where level 1 dropped directions
+    if (op > DF_APPLY1 && gs2 == 0) return false;
+    switch (op) {
+      case DF_APPLY1: set(T, kc, false, J.vk, kc, false, S, kc, R, kb, D[D_GS]); break;
+      case DF_C: set(S, kc, true, X, kc, false, J.gk, kc, k1, gs2, R); break;
+      case DF_R: set(S, kc, false, J.gk, kc, false, X, kc, R, gs2, k1); g.alpha = -1.0; g.acc = true; break;
+      case DF_GRAM2: set(X, kc, true, X, kc, false, J.gk, kc, gs2, gs2, R); break;
+      case DF_APPLY2: set(X, kc, false, J.vk, kc, false, T, kc, R, k2, gs2); break;
+      case DF_C2: set(S, kc, true, T, kc, false, J.gk, kc, k1, k2, R); break;
+      case DF_R2: set(S, kc, false, J.gk, kc, false, T, kc, R, k2, k1); g.alpha = -1.0; g.acc = true; break;
+      case DF_GRAM2B: set(T, kc, true, T, kc, false, J.gk, kc, D[D_G2S], D[D_G2S], R); break;
+      case DF_APPLY2B: set(T, kc, false, J.vk, kc, false, S + k1, kc, R, k2, D[D_G2S]); break;
+      default: return false;
+    }
+    return true;
+  }
   switch (kind) {
     case GK_GRAM_B:
       if (sub == 0) {
@@ -377,7 +420,15 @@ __global__ void k_apply_gate(const BondJob* jobs) {
     D[D_RF] = rf;
     D[D_GS] = rf ? k : 0;
     if (!rf) D[D_KQ] = M;
-    D[D_FB] = 0;  // read by a launch that runs for every item
+    // sizes read by launches that run for every item (0 = nothing to do);
+    // the range-finder steps set them for their own items
+    D[D_FB] = 0;
+    D[D_GS0] = 0;
+    D[D_K1] = 0;
+    D[D_GS2] = 0;
+    D[D_K2] = 0;
+    D[D_G2S] = 0;
+    D[D_FB2] = 0;
   }
   __shared__ double2 g[256];
   __shared__ double red[4];
@@ -434,6 +485,46 @@ __global__ void k_sketch_init(const BondJob* jobs) {
     const double rad = sqrt(-2.0 * log(u1));
     J.omega[(long long)row * J.k_cap + col] = mk<double>(rad * cos(6.283185307179586 * u2),
                                                         rad * sin(6.283185307179586 * u2));
+  }
+}
+
+// deflation bookkeeping, one thread per item (range finder jobs only).
+// stage 0: before level 1 (GS0 = GS); stage 1: after the level-1 eigenvalue
+// pass (largest Gram eigenvalue); stage 2: after level 1 (K1 = Kb, GS2 =
+// GS0 if directions were dropped); stage 3: before the level-2 second pass
+// (K2 <= GS0 - K1, G2S = K2); stage 4: after level 2 (Kb = K1 + K2).
+__global__ void k_defl_dims(const BondJob* jobs, int n_items, int stage, int side) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondJob& J = jobs[i];
+  int* D = J.dims;
+  if (!D[D_RF]) return;
+  const int kb = side ? D_KZ : D_KQ;
+  switch (stage) {
+    case 0: D[D_GS0] = D[D_GS]; D[D_GS2] = 0; D[D_K2] = 0; D[D_G2S] = 0; break;
+    case 1: J.norms[4] = J.wk[0]; break;
+    case 2: D[D_K1] = D[kb]; D[D_GS2] = (D[kb] < D[D_GS0]) ? D[D_GS0] : 0; D[D_K2] = 0; break;
+    case 3:  // the two levels together span at most the sketch width
+      if (D[D_GS2]) D[D_K2] = max(0, min(D[D_K2], D[D_GS0] - D[D_K1]));
+      D[D_G2S] = D[D_GS2] ? D[D_K2] : 0;
+      break;
+    case 4: if (D[D_GS2]) D[kb] = D[D_K1] + D[D_K2]; break;
+  }
+}
+
+// X = S (R x Kb) after a deflated orthonormalisation.  grid (blocks, items)
+__global__ void k_defl_copy(const BondJob* jobs, int side) {
+  const BondJob& J = jobs[blockIdx.y];
+  const int* D = J.dims;
+  if (!D[D_RF]) return;
+  double2* X = side ? J.za : J.ya;
+  const double2* S = side ? J.ya : J.za;
+  const int R = side ? D[D_N] : D[D_M], kb = side ? D[D_KZ] : D[D_KQ];
+  const long long tot = (long long)R * kb;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < tot;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / kb), c = (int)(idx - (long long)r * kb);
+    X[(long long)r * J.k_cap + c] = S[(long long)r * J.k_cap + c];
   }
 }
 

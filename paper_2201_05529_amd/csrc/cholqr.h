@@ -12,8 +12,8 @@
 //
 // A job is declined, and the eigenvalue pass runs for it instead, when n is
 // above CHOL_NMAX or a pivot is not a finite number above CHOL_PIVOT_FLOOR
-// times the largest diagonal entry of G: the kernel stores n in
-// dims[D_FB] for such a job and 0 otherwise.
+// times the largest diagonal entry of G: the kernel stores n in the
+// fallback dimension for such a job and 0 otherwise.
 //
 // Layout: one workgroup of CHOL_THREADS threads per job.  Thread t owns
 // column c = t mod CHOL_NMAX and the rows r = t / CHOL_NMAX + 8 m
@@ -33,14 +33,15 @@ constexpr int CHOL_ROWS = CHOL_THREADS / CHOL_NMAX;   // row groups (8)
 constexpr int CHOL_PER = CHOL_NMAX / CHOL_ROWS;       // rows per thread (16)
 constexpr double CHOL_PIVOT_FLOOR = 1e-6;
 
-// grid (items); dims[D_GS] is the Gram size, gk (ld k_cap) the Gram matrix
-__global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs) {
+// grid (items); dims[size_dim] is the Gram size, gk (ld k_cap) the Gram
+// matrix; the declined size goes to dims[fb_dim]
+__global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs, int size_dim, int fb_dim) {
   const BondJob& J = jobs[blockIdx.x];
   int* D = J.dims;
   const int t = threadIdx.x;
-  const int n = D[D_RF] != 0 ? D[D_GS] : 0;
+  const int n = D[D_RF] != 0 ? D[size_dim] : 0;
   if (n <= 0 || n > CHOL_NMAX) {
-    if (t == 0) D[D_FB] = n > 0 ? n : 0;
+    if (t == 0) D[fb_dim] = n > 0 ? n : 0;
     return;
   }
   const int ld = J.k_cap;
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs) 
     }
   }
   if (fail) {
-    if (t == 0) D[D_FB] = n;
+    if (t == 0) D[fb_dim] = n;
     return;
   }
   __syncthreads();  // dinv complete
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs) 
       if (i < n) J.vk[(long long)i * ld + c] = (i <= c) ? a[m] : mk<double>(0.0, 0.0);
     }
   }
-  if (t == 0) D[D_FB] = 0;
+  if (t == 0) D[fb_dim] = 0;
 }
 
 }  // namespace ptt

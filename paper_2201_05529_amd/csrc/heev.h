@@ -73,6 +73,8 @@ struct HeevJob {
   int scale;         // HeevScale applied to column k with lambda_k
   int* status;       // sticky error word (bit 1: no convergence, bit 4: non-finite, bit 8: size above n_cap)
   int noise_cluster; // 1: eigenvalues at the rounding level of zero form one cluster (stage 4b)
+  const double* abs_ref;  // RULE_RANK: if set, also drop eigenvalues <= abs_tol * (*abs_ref),
+  double abs_tol;         //            and allow no eigenpair at all
 };
 
 constexpr int HEEV_THREADS = 256;          // back-transformation kernel
@@ -394,7 +396,8 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     if (J.rule == RULE_FULL) {
       nvec = n;
     } else if (J.rule == RULE_RANK) {
-      while (nvec < n && w[nvec] > J.rank_tol * lam0 && w[nvec] > 0.0) ++nvec;
+      const double floor_abs = J.abs_ref ? J.abs_tol * fmax(*J.abs_ref, 0.0) : 0.0;
+      while (nvec < n && w[nvec] > J.rank_tol * lam0 && w[nvec] > floor_abs && w[nvec] > 0.0) ++nvec;
     } else {
       int npos = 0;
       while (npos < n && w[npos] > 0.0) ++npos;
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
         }
       }
     }
-    if (nvec < 1 && lam0 > 0.0) nvec = 1;
+    if (nvec < 1 && lam0 > 0.0 && !(J.rule == RULE_RANK && J.abs_ref)) nvec = 1;
     if (!(lam0 == lam0) || isinf(lam0)) atomicOr(J.status, 4);
     s_nvec = nvec;
     *J.nvec_out = nvec;

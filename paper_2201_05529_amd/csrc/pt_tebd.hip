@@ -48,6 +48,8 @@ struct Sublayer {
   HeevJob* heev_oz = nullptr;    // device [n]
   HeevJob* heev_oyb = nullptr;   // device [n]: eigenvalue form of the second pass (size dims[D_FB])
   HeevJob* heev_ozb = nullptr;   // device [n]
+  HeevJob* heev_l2 = nullptr;    // device [n]: deflation level 2 (size dims[D_GS2])
+  HeevJob* heev_l2b = nullptr;   // device [n]: its second pass in eigenvalue form (size dims[D_FB2])
   HeevJob* heev_rr = nullptr;    // device [n]
   ptt::RefineJob* ref_b = nullptr;  // device [2 n]: B_L, B_R
   ptt::RefineJob* ref_d = nullptr;  // device [n]
@@ -73,6 +75,7 @@ struct pt_tebd {
   unsigned long long seed = 0;
   int power_iters = 2;
   bool cholqr = true;      // second orthonormalisation pass by Cholesky QR
+  bool deflate = true;     // two-level (deflated) orthonormalisation of the range finder's bases
   int oversample = 64;
   int refine_levels = 0;   // block refinement levels (PT_TEBD_REFINE_LEVELS)
   double refine_tau = 1e-4;
@@ -159,7 +162,7 @@ struct DevPtrs {
   std::vector<double2*> h_refl[2];
   std::vector<double*> h_tri[2], h_work[2], h_z[2];
   BondJob* jobs[2];
-  HeevJob *hb[2], *hoy[2], *hoz[2], *hoyb[2], *hozb[2], *hrr[2], *hrb[2], *hrd[2];
+  HeevJob *hb[2], *hoy[2], *hoz[2], *hoyb[2], *hozb[2], *hl2[2], *hl2b[2], *hrr[2], *hrb[2], *hrd[2];
   ptt::RefineJob *rb[2], *rd[2];
   std::vector<int*> blk;   // per slot: 3 x [2]
 };
@@ -209,7 +212,7 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
   for (int s = 0; s < c.n_slots; ++s) {
     BondJob J{};
     J.dims = bp.take<int>(ptt::D_COUNT);
-    J.norms = bp.take<double>(4);
+    J.norms = bp.take<double>(8);
     J.bl = bp.take<double2>(rl * nb);
     J.br = bp.take<double2>(nb * rl);
     J.gl = bp.take<double2>(nb * nb);
@@ -261,6 +264,8 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     P.hoz[par] = bp.take<HeevJob>(n);
     P.hoyb[par] = bp.take<HeevJob>(n);
     P.hozb[par] = bp.take<HeevJob>(n);
+    P.hl2[par] = bp.take<HeevJob>(n);
+    P.hl2b[par] = bp.take<HeevJob>(n);
     P.hrr[par] = bp.take<HeevJob>(n);
     P.hrb[par] = bp.take<HeevJob>(2 * n);
     P.hrd[par] = bp.take<HeevJob>(n);
@@ -478,35 +483,68 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   // form for the jobs it declines (dims[D_FB] = 0 for the others)
   auto second_pass = [&](const HeevJob* eig, const HeevJob* fallback) {
     if (h->cholqr) {
-      ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J);
+      ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J, ptt::D_GS, ptt::D_FB);
       launch_heev(st, fallback, n, c.kc);
     } else {
       launch_heev(st, eig, n, c.kc);
     }
   };
-  auto orth_y = [&]() {
-    launch_gemm(st, J, n, ptt::GK_GRAM_YA, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oy, n, c.kc, h->cholqr ? 0 : 2);
-    launch_gemm(st, J, n, ptt::GK_APPLY_YA, 1, c.dn, c.kc);
-    copy_dim(ptt::D_GS, ptt::D_KQ);
-    launch_gemm(st, J, n, ptt::GK_GRAM_YB, 1, c.kc, c.kc);
-    second_pass(S.heev_oy, S.heev_oyb);
-    launch_gemm(st, J, n, ptt::GK_APPLY_YB, 1, c.dn, c.kc);
+  auto defl_dims = [&](int stage, int side) {
+    ptt::k_defl_dims<<<(n + 63) / 64, 64, 0, st>>>(J, n, stage, side);
   };
-  orth_y();
+  auto df = [&](int op, int side, int m_cap, int n_cap) { launch_gemm(st, J, n, ptt::GK_DF + 2 * op + side, 1, m_cap, n_cap); };
+  // Orthonormal basis of the sketch X (side 0: ya, rows M; side 1: za, rows
+  // N).  Level 1: eigenvalues of X^H X with the numerical-rank rule
+  // (directions below 1e-15 of the largest eigenvalue dropped), then a
+  // Cholesky pass.  A Gram matrix resolves singular values only down to
+  // ~3e-8 of the largest, so the dropped part is not noise in general:
+  // level 2 takes the residual X - Q1 Q1^H X (two passes), orthonormalises it
+  // the same way relative to its own scale (keeping singular values above
+  // 1e-13 of the sketch's largest), against Q1 once more, and appends it.
+  auto orth = [&](int side) {
+    const int kb = side ? ptt::D_KZ : ptt::D_KQ;
+    const HeevJob* h1 = side ? S.heev_oz : S.heev_oy;
+    const HeevJob* h1b = side ? S.heev_ozb : S.heev_oyb;
+    if (h->deflate) defl_dims(0, side);
+    launch_gemm(st, J, n, side ? ptt::GK_GRAM_ZA : ptt::GK_GRAM_YA, 1, c.kc, c.kc);
+    launch_heev(st, h1, n, c.kc, h->cholqr ? 0 : 2);
+    if (h->deflate) defl_dims(1, side);
+    launch_gemm(st, J, n, side ? ptt::GK_APPLY_ZA : ptt::GK_APPLY_YA, 1, c.dn, c.kc);
+    copy_dim(ptt::D_GS, kb);
+    launch_gemm(st, J, n, side ? ptt::GK_GRAM_ZB : ptt::GK_GRAM_YB, 1, c.kc, c.kc);
+    second_pass(h1, h1b);
+    if (!h->deflate) {
+      launch_gemm(st, J, n, side ? ptt::GK_APPLY_ZB : ptt::GK_APPLY_YB, 1, c.dn, c.kc);
+      return;
+    }
+    df(ptt::DF_APPLY1, side, c.dn, c.kc);  // Q1 into the scratch basis
+    defl_dims(2, side);
+    for (int pass = 0; pass < 2; ++pass) {
+      df(ptt::DF_C, side, c.kc, c.kc);
+      df(ptt::DF_R, side, c.dn, c.kc);
+    }
+    df(ptt::DF_GRAM2, side, c.kc, c.kc);
+    launch_heev(st, S.heev_l2, n, c.kc);
+    df(ptt::DF_APPLY2, side, c.dn, c.kc);
+    df(ptt::DF_C2, side, c.kc, c.kc);
+    df(ptt::DF_R2, side, c.dn, c.kc);
+    defl_dims(3, side);
+    df(ptt::DF_GRAM2B, side, c.kc, c.kc);
+    if (h->cholqr) ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J, ptt::D_G2S, ptt::D_FB2);
+    else copy_dim(ptt::D_FB2, ptt::D_G2S);
+    launch_heev(st, S.heev_l2b, n, c.kc);
+    df(ptt::DF_APPLY2B, side, c.dn, c.kc);
+    defl_dims(4, side);
+    ptt::k_defl_copy<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J, side);
+  };
+  orth(0);
   for (int it = 0; it < h->power_iters; ++it) {
     launch_gemm(st, J, n, ptt::GK_DH_Q, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KQ);
-    launch_gemm(st, J, n, ptt::GK_GRAM_ZA, 1, c.kc, c.kc);
-    launch_heev(st, S.heev_oz, n, c.kc, h->cholqr ? 0 : 2);
-    launch_gemm(st, J, n, ptt::GK_APPLY_ZA, 1, c.dn, c.kc);
-    copy_dim(ptt::D_GS, ptt::D_KZ);
-    launch_gemm(st, J, n, ptt::GK_GRAM_ZB, 1, c.kc, c.kc);
-    second_pass(S.heev_oz, S.heev_ozb);
-    launch_gemm(st, J, n, ptt::GK_APPLY_ZB, 1, c.dn, c.kc);
+    orth(1);
     launch_gemm(st, J, n, ptt::GK_D_Z, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KZ);
-    orth_y();
+    orth(0);
   }
   launch_gemm(st, J, n, ptt::GK_QH_D, 1, c.kc, c.dn);
   ptt::k_resid_copy<<<dim3(elem_blocks((long long)c.dn * c.dn), n), kThreads, 0, st>>>(J);
@@ -616,6 +654,8 @@ void fill_heev(HeevJob& H, double2* a, int lda, int* n_ptr, double* w, double2* 
   H.n_cap = n_cap; H.nvec_out = nvec; H.rule = rule; H.eps = eps; H.cap = capv; H.extra_tail = extra;
   H.rank_tol = rank_tol; H.v = v; H.ldv = ldv; H.scale = scale; H.status = status;
   H.noise_cluster = env_int("PT_TEBD_HEEV_NOISE", 1) != 0;
+  H.abs_ref = nullptr;
+  H.abs_tol = 0.0;
 }
 
 }  // namespace
@@ -655,6 +695,10 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   // workload at its chi cap is off by ~1e-6 in the observables
   h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 2));
   h->cholqr = env_int("PT_TEBD_CHOLQR", 1) != 0;
+  // the Gram matrix of a sketch resolves directions down to ~3e-8 of its
+  // largest singular value; truncation thresholds below 1e-8 need the
+  // deflated second level of the range finder's orthonormalisation
+  h->deflate = env_int("PT_TEBD_DEFLATE", cfg->svd_rel_cutoff < 1e-8 ? 1 : 0) != 0;
   // Gram matrices resolve singular values down to ~1e-8 of the largest,
   // which is where a truncation threshold eps ~ 1e-7 cuts: one level of
   // block refinement resolves the block below 1e-4 of the largest relative
@@ -803,13 +847,15 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     S.heev_oz = P.hoz[par];
     S.heev_oyb = P.hoyb[par];
     S.heev_ozb = P.hozb[par];
+    S.heev_l2 = P.hl2[par];
+    S.heev_l2b = P.hl2b[par];
     S.heev_rr = P.hrr[par];
     S.ref_b = P.rb[par];
     S.ref_d = P.rd[par];
     S.heev_ref_b = P.hrb[par];
     S.heev_ref_d = P.hrd[par];
     std::vector<HeevJob> hb2(2 * std::max(n, 1)), hoy(std::max(n, 1)), hoz(std::max(n, 1)), hrr(std::max(n, 1));
-    std::vector<HeevJob> hoyb(std::max(n, 1)), hozb(std::max(n, 1));
+    std::vector<HeevJob> hoyb(std::max(n, 1)), hozb(std::max(n, 1)), hl2(std::max(n, 1)), hl2b(std::max(n, 1));
     std::vector<HeevJob> hrb(2 * std::max(n, 1)), hrd(std::max(n, 1));
     std::vector<ptt::RefineJob> rb(2 * std::max(n, 1)), rd(std::max(n, 1));
     for (int i = 0; i < n; ++i) {
@@ -842,6 +888,16 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
       hoyb[i].n_ptr = J.dims + ptt::D_FB;
       hozb[i] = hoz[i];
       hozb[i].n_ptr = J.dims + ptt::D_FB;
+      // deflation level 2: residual directions above 1e-26 of the level-1
+      // basis's largest Gram eigenvalue (singular values above 1e-13 of it)
+      hl2[i] = hoy[i];
+      hl2[i].n_ptr = J.dims + ptt::D_GS2;
+      hl2[i].nvec_out = J.dims + ptt::D_K2;
+      hl2[i].abs_ref = J.norms + 4;
+      hl2[i].abs_tol = 1e-26;
+      hl2b[i] = hoy[i];
+      hl2b[i].n_ptr = J.dims + ptt::D_FB2;
+      hl2b[i].nvec_out = J.dims + ptt::D_K2;
       fill_heev(hrr[i], J.gk, c.kc, J.dims + ptt::D_GS, J.wk, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
                 P.h_z[0][i], c.nh, J.dims + ptt::D_CHI, ptt::RULE_FULL, J.eps, cfg->chi_max, J.norms + 2, 0.0,
                 J.vk, c.kc, ptt::SCALE_NONE, st0);
@@ -882,6 +938,8 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
                 check(hipMemcpyAsync(S.heev_oz, hoz.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_oyb, hoyb.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_ozb, hozb.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_l2, hl2.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
+                check(hipMemcpyAsync(S.heev_l2b, hl2b.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_rr, hrr.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_ref_b, hrb.data(), 2 * n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
                 check(hipMemcpyAsync(S.heev_ref_d, hrd.data(), n * sizeof(HeevJob), hipMemcpyHostToDevice, st), hp, "jobs") &&
