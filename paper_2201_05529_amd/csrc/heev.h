@@ -753,52 +753,39 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_backtransform_kernel(const 
   if (c0 >= nvec) return;
   const int ncol = min(HEEV_BT_COLS, nvec - c0);
   extern __shared__ double2 zs[];  // [n][HEEV_BT_COLS]
-  __shared__ double2 dots[HEEV_THREADS / 64][HEEV_BT_COLS];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ double2 dots[1][HEEV_BT_COLS];
+  const int tid = threadIdx.x;
   const int nc = J.n_cap;
   for (int e = tid; e < n * HEEV_BT_COLS; e += HEEV_THREADS) {
     const int i = e / HEEV_BT_COLS, c = e - i * HEEV_BT_COLS;
     zs[e] = mk<double>(c < ncol ? J.z[(size_t)i * nc + c0 + c] : 0.0, 0.0);
   }
   const double2* taus = reinterpret_cast<const double2*>(J.tri + 2 * J.n_cap);
+  // 32 lanes per column: thread (c, l) owns rows l, l + 32, ... of column c
+  // below the reflector's start, so a column's dot product is one reduction
+  // over half a wave (five shuffles per real part) with no cross-wave sum
+  constexpr int LPC = HEEV_THREADS / HEEV_BT_COLS;  // 32
+  const int cc = tid / LPC, ll = tid % LPC;
   __syncthreads();
   for (int j = n - 2; j >= 0; --j) {
     const double2 tau = taus[j];
     if (tau.x == 0.0 && tau.y == 0.0) continue;
     const int m = n - j - 1;
     const double2* v = J.refl + (size_t)j * nc;
-    // s_c = sum_i conj(v_i) z[j+1+i][c]
-    double2 part[HEEV_BT_COLS];
+    // s_c = tau * sum_i conj(v_i) z[j+1+i][c]
+    double2 part = mk<double>(0.0, 0.0);
+    for (int i = ll; i < m; i += LPC) cfmaconj<double>(part, v[i], zs[(j + 1 + i) * HEEV_BT_COLS + cc]);
 #pragma unroll
-    for (int c = 0; c < HEEV_BT_COLS; ++c) part[c] = mk<double>(0.0, 0.0);
-    for (int i = tid; i < m; i += HEEV_THREADS) {
-      const double2 vi = v[i];
-#pragma unroll
-      for (int c = 0; c < HEEV_BT_COLS; ++c) cfmaconj<double>(part[c], vi, zs[(j + 1 + i) * HEEV_BT_COLS + c]);
+    for (int off = LPC / 2; off > 0; off >>= 1) {
+      part.x += __shfl_xor(part.x, off, 64);
+      part.y += __shfl_xor(part.y, off, 64);
     }
-#pragma unroll
-    for (int c = 0; c < HEEV_BT_COLS; ++c) {
-      part[c].x = warp_sum(part[c].x);
-      part[c].y = warp_sum(part[c].y);
-    }
-    if (lane == 0)
-#pragma unroll
-      for (int c = 0; c < HEEV_BT_COLS; ++c) dots[wid][c] = part[c];
+    if (ll == 0) dots[0][cc] = cmul<double>(tau, part);
     __syncthreads();
-    double2 s[HEEV_BT_COLS];
-#pragma unroll
-    for (int c = 0; c < HEEV_BT_COLS; ++c) {
-      double2 acc = mk<double>(0.0, 0.0);
-      for (int w2 = 0; w2 < HEEV_THREADS / 64; ++w2) acc = cadd<double>(acc, dots[w2][c]);
-      s[c] = cmul<double>(tau, acc);
-    }
-    for (int i = tid; i < m; i += HEEV_THREADS) {
-      const double2 vi = v[i];
-#pragma unroll
-      for (int c = 0; c < HEEV_BT_COLS; ++c) {
-        double2& zz = zs[(j + 1 + i) * HEEV_BT_COLS + c];
-        zz = csub<double>(zz, cmul<double>(s[c], vi));
-      }
+    const double2 sc = dots[0][cc];
+    for (int i = ll; i < m; i += LPC) {
+      double2& zz = zs[(j + 1 + i) * HEEV_BT_COLS + cc];
+      zz = csub<double>(zz, cmul<double>(sc, v[i]));
     }
     __syncthreads();
   }
