@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs, 
   __shared__ double2 rbuf[2][CHOL_NMAX];
   __shared__ double2 cbuf[2][CHOL_NMAX];
   __shared__ double dinv[CHOL_NMAX];
+  __shared__ double piv[2][4];  // p, 1/p, sqrt(p), 1/sqrt(p) of the current step
   __shared__ double red[CHOL_THREADS / 64];
 
   // upper triangle of G into registers; largest diagonal entry
@@ -80,13 +81,22 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_chol_inv(const BondJob* jobs, 
     if (rg == (k % CHOL_ROWS) && c >= k && c < n) {
 #pragma unroll
       for (int m = 0; m < CHOL_PER; ++m)
-        if (m == k / CHOL_ROWS) buf[c] = a[m];
+        if (m == k / CHOL_ROWS) {
+          buf[c] = a[m];
+          if (c == k) {  // the pivot's owner does the divisions once for everyone
+            const double p = a[m].x, r = sqrt(p);
+            piv[k & 1][0] = p;
+            piv[k & 1][1] = 1.0 / p;
+            piv[k & 1][2] = r;
+            piv[k & 1][3] = 1.0 / r;
+            dinv[k] = 1.0 / r;
+          }
+        }
     }
     __syncthreads();
-    const double p = buf[k].x;
+    const double p = piv[k & 1][0];
     if (!(p > floor_piv) || !(p < INFINITY)) { fail = true; break; }  // same value in every thread
-    const double rkk = sqrt(p), ip = 1.0 / p, irk = 1.0 / rkk;
-    if (t == 0) dinv[k] = irk;
+    const double ip = piv[k & 1][1], rkk = piv[k & 1][2], irk = piv[k & 1][3];
     if (c > k && c < n) {
       const double2 bc = buf[c];
 #pragma unroll
