@@ -683,7 +683,11 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
       for (int j = nz ? k : k + 1; j < e; ++j) {
         // reference vectors: [na, j) and [e, nb)
         const int r1 = j - na, nref = r1 + (nb - e);
-        for (int pass = 0; pass < 2; ++pass) {
+        // the null-space members are random vectors already projected off
+        // every other vector and well conditioned among themselves: one
+        // pass, the block Gram-Schmidt of stage 6 (or the caller's Cholesky
+        // pass) removes the second-order overlaps
+        for (int pass = 0; pass < (nz ? 1 : 2); ++pass) {
           // dots[t] = z_p(t) . z_j: 256 references at a time, the rows split
           // over four thread groups (partial sums in LDS, added in a fixed
           // order); rows of Z are contiguous in the vector index
