@@ -49,7 +49,8 @@ typedef enum {
   PT_TEBD_EDEVICE = -3,  /* a HIP runtime call failed                        */
   PT_TEBD_ENUMERIC = -4, /* non-finite value or zero norm met on the device  */
   PT_TEBD_ENOCONV = -5,  /* an iterative eigensolver stage did not converge  */
-  PT_TEBD_ERANGE = -6    /* stepped past the end of a PT-MPO                 */
+  PT_TEBD_ERANGE = -6    /* stepped past the end of a PT-MPO, or a size read
+                            on the device exceeded its workspace (internal) */
 } pt_tebd_status;
 
 typedef enum {
