@@ -817,6 +817,9 @@ __global__ void __launch_bounds__(GEMM_THREADS) heev_orth_gemm(const HeevJob* jo
   if (n <= 0 || n > J.n_cap) return;
   const int nvec = *J.nvec_out;
   if (nvec < 2) return;
+  // only the strictly upper part of V^H V is used: tiles below the
+  // diagonal are skipped
+  if (kind == 0 && blockIdx.x > blockIdx.y) return;
   if (kind == 0)
     gemm_tile<double>(J.v, J.ldv, true, J.v, J.ldv, false, orth_g(J), J.n_cap, nvec, nvec, n,
                       mk<double>(1.0, 0.0), false, blockIdx.x, blockIdx.y, sm);
@@ -842,26 +845,34 @@ __global__ void heev_orth_mfix(const HeevJob* jobs) {
 }
 
 // V <- T with unit columns (from_t), or V's own columns renormalised; the
-// last call also applies the column scaling.  One thread per column.
-// grid (ceil(n_cap / 256), jobs)
+// last call also applies the column scaling.  64 columns per block (one per
+// lane), rows split over the four waves; the partial norms are added in a
+// fixed order.  grid (ceil(n_cap / 64), jobs)
 __global__ void heev_orth_norm(const HeevJob* jobs, int from_t, int final_pass) {
   const HeevJob& J = jobs[blockIdx.y];
   const int n = *J.n_ptr;
   if (n <= 0 || n > J.n_cap) return;
   const int nvec = *J.nvec_out;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nvec) return;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6, ng = blockDim.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  __shared__ double part[4][64];
   const bool use_t = from_t && nvec >= 2;
   const double2* src = use_t ? orth_t(J) : J.v;
   const int lds = use_t ? J.n_cap : J.ldv;
   double acc = 0.0;
-  for (int r = 0; r < n; ++r) acc += cabs2<double>(src[(size_t)r * lds + k]);
-  double f = acc > 0.0 ? 1.0 / sqrt(acc) : 0.0;
+  if (k < nvec)
+    for (int r = g; r < n; r += ng) acc += cabs2<double>(src[(size_t)r * lds + k]);
+  part[g][lane] = acc;
+  __syncthreads();
+  if (k >= nvec) return;
+  double tot = 0.0;
+  for (int q = 0; q < ng; ++q) tot += part[q][lane];
+  double f = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
   if (final_pass && J.scale != SCALE_NONE) {
     const double lam = fmax(J.w[k], 1e-300);
     f *= (J.scale == SCALE_INV_SQRT) ? 1.0 / sqrt(lam) : sqrt(lam);
   }
-  for (int r = 0; r < n; ++r) J.v[(size_t)r * J.ldv + k] = cscale<double>(src[(size_t)r * lds + k], f);
+  for (int r = g; r < n; r += ng) J.v[(size_t)r * J.ldv + k] = cscale<double>(src[(size_t)r * lds + k], f);
 }
 
 }  // namespace ptt

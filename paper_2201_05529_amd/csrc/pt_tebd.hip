@@ -419,7 +419,7 @@ void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap, int
   ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, shm, st>>>(jobs);
   const int tiles = (n_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM;
   const dim3 gg(tiles, tiles, n_jobs);
-  const dim3 gn((n_cap + 255) / 256, n_jobs);
+  const dim3 gn((n_cap + 63) / 64, n_jobs);
   if (passes == 0) {
     ptt::heev_orth_norm<<<gn, 256, 0, st>>>(jobs, 0, 1);
     return;
