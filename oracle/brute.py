@@ -18,8 +18,13 @@ the observables of pt_tebd.py.
   PT-TEBD schedule (or the exact chain half-step propagator), bath factors
   applied in the coupling eigenbasis.
 
-Pinned by tests/test_oracle_brute.py (zero-coupling dense expm of an
-independently built Liouvillian; closed forms).
+It is pinned on its own terms in tests/test_oracle_pt_tebd.py: the
+zero-coupling dense expm of an independently built Liouvillian, and the
+closed forms of closed_forms.py (through the PT-TEBD runs it must match).
+``BruteForce.correlate_multi`` inserts left- or right-acting single-site
+super-operators into the dense augmented state (eq.
+two-time-corr-decomposed); its own pin is a two-point function of a
+bath-free chain evaluated as Tr[B e^{L t} A rho] with the dense propagator.
 """
 import numpy as np
 import scipy.linalg
@@ -174,6 +179,42 @@ class BruteForce:
                 self._bath_step(bath)
             self._half_step()
             self.step_index += 1
+
+    def insert(self, site, op, side="L"):
+        """Apply C rho (side "L") or rho C (side "R") on one site of the
+        augmented state (every history axis is untouched)."""
+        op = np.asarray(op, dtype=np.complex128)
+        sop = lv.left_mult(op) if side == "L" else lv.right_mult(op)
+        self._apply_on_axes(sop, [("site", site)])
+
+    def correlate_multi(self, insertions, site_b, op_b, n_steps):
+        """Same contract as the PT-TEBD oracle's correlate_multi: a copy of
+        the dense augmented state receives the insertions (m_p, n_p, C_p,
+        side_p) at step offsets m_p and is propagated; out[j] is
+        Tr[B X] / Tr rho(t) at offset m_P + j."""
+        import copy as _copy
+        tr0 = self.trace()
+        fork = _copy.deepcopy(self)
+        offset = 0
+        for m, site, op, side in insertions:
+            fork.step(m - offset)
+            offset = m
+            fork.insert(site, op, side)
+        out = []
+        for j in range(n_steps + 1):
+            if j:
+                fork.step(1)
+            out.append(fork.unnormalised(site_b, op_b) / tr0)
+        return np.array(out)
+
+    def unnormalised(self, site, op):
+        """Tr[op_site X] without dividing by Tr X."""
+        v = self.chain_vector().reshape([self.d2] * self.n_sites)
+        t = lv.trace_vector(self.d)
+        o = lv.observable_vector(op)
+        for n in range(self.n_sites - 1, -1, -1):
+            v = v @ (o if n == site else t)
+        return v
 
     def chain_vector(self):
         """Site-major vec(rho_chain): every history axis summed (all-ones caps)."""

@@ -45,6 +45,11 @@ def left_mult(a):
     return sandwich(a, np.eye(a.shape[0], dtype=np.complex128))
 
 
+def right_mult(a):
+    """Super-operator of rho -> rho a (right-acting C^R of Appendix A.4)."""
+    return sandwich(np.eye(a.shape[0], dtype=np.complex128), a)
+
+
 def hamiltonian_liouvillian(h):
     """-i[h, .] in row-major Liouville space."""
     one = np.eye(h.shape[0], dtype=np.complex128)

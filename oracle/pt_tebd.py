@@ -25,10 +25,11 @@ Two-site gate (Appendix A.2, Fig. tensor-network-contraction (c)-(h)):
 Truncation (Appendix A.2): the smallest rank with the 2-norm of the
 discarded singular values strictly below eps times the largest.  Readings:
 exact zeros are never kept, the rank is at least 1, the eps rule comes first
-and the chi_max cap second.  Neighbouring values within a relative gap of
-1e-6 form a multiplet, whose kept subspace is not determined by the values:
-an eps cut inside a multiplet moves to its end (the discarded tail only
-shrinks) and a cap that splits one drops it whole.
+and the chi_max cap second.  The eps cut is the smallest such rank, with no
+adjustment.  Only the cap has a tie rule: where it would keep one value of a
+pair equal to within 1e-10 of the largest singular value, the kept subspace
+is not determined by the values, so the cap moves down to the start of that
+degenerate run.
 
 PT absorption (Appendix A.2, Fig. tensor-network-contraction (i)-(j)):
   Gamma_n[a,s,e',b] <- sum_{e, s_in} P_k[e,e',s,s_in] Gamma_n[a,s_in,e,b].
@@ -54,11 +55,11 @@ from . import gates as gt
 from . import liouville as lv
 
 
-TIE_TOLERANCE = 1e-6  # relative gap below which neighbouring singular values form a multiplet
+CAP_TIE = 1e-10  # |sigma_c - sigma_{c+1}| below CAP_TIE * sigma_1 counts as degenerate at the cap
 
 
 def truncation_rank(sv, eps, chi_max=None):
-    """Truncated rank for descending singular values ``sv``."""
+    """Truncated rank for descending singular values ``sv`` (Appendix A.2)."""
     sv = np.asarray(sv, dtype=np.float64)
     n_pos = int(np.count_nonzero(sv > 0.0))
     if n_pos == 0:
@@ -70,14 +71,10 @@ def truncation_rank(sv, eps, chi_max=None):
         if tail[c] < eps * sv[0]:
             rank = c
             break
-    # a cut inside a multiplet (consecutive singular values within a relative
-    # gap of TIE_TOLERANCE) leaves the kept subspace undetermined; the eps cut
-    # is moved to the multiplet's end, which only shrinks the discarded tail
-    while rank < n_pos and sv[rank - 1] - sv[rank] < TIE_TOLERANCE * sv[rank - 1]:
-        rank += 1
     if chi_max is not None and rank > chi_max:
         rank = chi_max
-        while rank > 1 and sv[rank - 1] - sv[rank] < TIE_TOLERANCE * sv[rank - 1]:
+        # the cap splits a degenerate run: keep none of it
+        while rank > 1 and sv[rank - 1] - sv[rank] < CAP_TIE * sv[0]:
             rank -= 1
     return rank
 
@@ -102,7 +99,17 @@ class AugmentedMPS:
         return [g.shape[2] for g in self.gammas]
 
 
-def two_site_update(mps, bond, gate, eps, chi_max, stats=None):
+def svd(mat, driver="gesdd"):
+    """Thin SVD by LAPACK: numpy's default divide-and-conquer driver, or
+    scipy's gesvd (QR iteration), a second correct implementation used to
+    measure how far two LAPACK drivers' trajectories drift apart."""
+    if driver == "gesdd":
+        return np.linalg.svd(mat, full_matrices=False)
+    import scipy.linalg
+    return scipy.linalg.svd(mat, full_matrices=False, lapack_driver=driver)
+
+
+def two_site_update(mps, bond, gate, eps, chi_max, stats=None, driver="gesdd"):
     """Appendix A.2 sequence (c)-(h) on sites bond, bond+1."""
     d2 = mps.d2
     g_l, g_r = mps.gammas[bond], mps.gammas[bond + 1]
@@ -115,9 +122,9 @@ def two_site_update(mps, bond, gate, eps, chi_max, stats=None):
     b_r = (g_r * lam_r[None, None, None, :]).reshape(b * d2, f * c)
 
     # (d-e)
-    u_l, s_l, vh_l = np.linalg.svd(b_l, full_matrices=False)
+    u_l, s_l, vh_l = svd(b_l, driver)
     n_l = truncation_rank(s_l, eps)
-    u_r, s_r, vh_r = np.linalg.svd(b_r, full_matrices=False)
+    u_r, s_r, vh_r = svd(b_r, driver)
     n_r = truncation_rank(s_r, eps)
     x_mat = (s_l[:n_l, None] * vh_l[:n_l]).reshape(n_l, d2, b)      # [l, s, b]
     y_mat = (u_r[:, :n_r] * s_r[None, :n_r]).reshape(b, d2, n_r)    # [b, t, r]
@@ -130,7 +137,7 @@ def two_site_update(mps, bond, gate, eps, chi_max, stats=None):
     d_mat = d_ten.reshape(n_l * d2, d2 * n_r)
 
     # (f-g)
-    u_d, s_d, vh_d = np.linalg.svd(d_mat, full_matrices=False)
+    u_d, s_d, vh_d = svd(d_mat, driver)
     chi = truncation_rank(s_d, eps, chi_max)
     norm = np.linalg.norm(s_d[:chi])
     mps.lams[bond + 1] = s_d[:chi] / norm
@@ -214,15 +221,17 @@ class Problem:
 
 
 class Engine:
-    def __init__(self, problem, mode="ch"):
+    def __init__(self, problem, mode="ch", svd_driver="gesdd"):
         self.p = problem
         self.mode = mode
+        self.svd_driver = svd_driver
         self.mps = AugmentedMPS(problem.rho0, problem.d)
         self.stats = []
 
     def _gate(self, mps, bond):
         if self.mode == "ch":
-            two_site_update(mps, bond, self.p.gates[bond], self.p.eps, self.p.chi_max, self.stats)
+            two_site_update(mps, bond, self.p.gates[bond], self.p.eps, self.p.chi_max, self.stats,
+                            self.svd_driver)
         else:
             two_site_update_theta(mps, bond, self.p.gates[bond], self.p.eps, self.p.chi_max)
 
@@ -305,12 +314,32 @@ class Engine:
     def correlate(self, site_a, op_a, site_b, op_b, n_steps):
         """C(j) = Tr[B X(t + j dt)] / Tr rho(t), j = 0..n_steps, where
         X(t) = A rho(t) is propagated from a copy of the augmented state."""
+        return self.correlate_multi([(0, site_a, op_a, "L")], site_b, op_b, n_steps)
+
+    def correlate_multi(self, insertions, site_b, op_b, n_steps):
+        """Multi-time correlation of eq. two-time-corr-decomposed, from the
+        current step t: a copy X of the augmented state is propagated, and
+        at step offset m_p (non-decreasing, m_1 >= 0) the super-operator of
+        C_p acts on site n_p, from the left (C rho, side "L") or, for
+        out-of-time-ordered correlations, from the right (rho C, side "R").
+        insertions = [(m_p, n_p, C_p, side_p), ...].  Returns
+        out[j] = Tr[B X(t + (m_P + j) dt)] / Tr rho(t), j = 0..n_steps, with
+        m_P the last offset.  Never normalised by the trace of X."""
         tr0 = self.trace()
         fork = self.mps.copy()
-        apply_site_superop(fork, site_a, lv.left_mult(np.asarray(op_a, dtype=np.complex128)))
         t = lv.trace_vector(self.p.d)
         vecs = [t] * fork.n_sites
         vecs[site_b] = lv.observable_vector(op_b)
+        offset = 0
+        for m, site, op, side in insertions:
+            if m < offset:
+                raise ValueError("insertion offsets must be non-decreasing")
+            for _ in range(m - offset):
+                self.step_state(fork)
+            offset = m
+            op = np.asarray(op, dtype=np.complex128)
+            sop = lv.left_mult(op) if side == "L" else lv.right_mult(op)
+            apply_site_superop(fork, site, sop)
         out = [self.contract(fork, vecs) / tr0]
         for _ in range(n_steps):
             self.step_state(fork)

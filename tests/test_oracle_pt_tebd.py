@@ -161,6 +161,69 @@ def test_correlation_special_cases():
     assert eng.mps.step == 2   # the main state is untouched
 
 
+def test_brute_force_correlation_matches_hilbert_space():
+    # pin of BruteForce.correlate_multi on its own: a closed chain (no bath,
+    # no GKSL terms) evolved with the exact propagator, against the
+    # Heisenberg-picture two-point function Tr[B U(tau) A rho(t) U(tau)^dag]
+    # (and Tr[B U (rho A) U^dag] for the right-acting insertion) computed in
+    # Hilbert space from the eigendecomposition of H
+    wl = W.random_small_chain(61, 3)
+    n, dt = 3, wl["dt"]
+    bf = brute.BruteForce(wl["h_site"], wl["h_bond"], wl["rho0"], dt, split="exact")
+    bf.step(2)
+    h = sum(lv.embed_site_operator(wl["h_site"][i], i, n, 2) for i in range(n))
+    h = h + sum(lv.embed_bond_operator(wl["h_bond"][b], b, n, 2) for b in range(n - 1))
+    w, v = np.linalg.eigh(h)
+
+    def u(t):
+        return (v * np.exp(-1j * w * t)) @ v.conj().T
+
+    rho0 = wl["rho0"][0]
+    for r in wl["rho0"][1:]:
+        rho0 = np.kron(rho0, r)
+    rho_t = u(2 * dt) @ rho0 @ u(2 * dt).conj().T
+    a = lv.embed_site_operator(SX, 0, n, 2)
+    b = lv.embed_site_operator(SZ, 2, n, 2)
+    for side in ("L", "R"):
+        c = bf.correlate_multi([(0, 0, SX, side)], 2, SZ, 5)
+        x0 = a @ rho_t if side == "L" else rho_t @ a
+        ref = [np.trace(b @ u(j * dt) @ x0 @ u(j * dt).conj().T) / np.trace(rho_t) for j in range(6)]
+        assert np.abs(c - np.array(ref)).max() < 1e-12
+    # three-time form: A at t, C at t + 2 dt, B read from t + 2 dt on
+    cop = lv.embed_site_operator(SY, 1, n, 2)
+    c = bf.correlate_multi([(0, 0, SX, "L"), (2, 1, SY, "L")], 2, SZ, 3)
+    x2 = cop @ (u(2 * dt) @ (a @ rho_t) @ u(2 * dt).conj().T)
+    ref = [np.trace(b @ u(j * dt) @ x2 @ u(j * dt).conj().T) / np.trace(rho_t) for j in range(4)]
+    assert np.abs(c - np.array(ref)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,bath_sites,k_cut", [(2, (0,), 3), (3, (0, 2), 2), (3, (1,), 3)])
+def test_correlate_matches_brute_force_with_baths(n, bath_sites, k_cut):
+    # Engine.correlate / correlate_multi against the dense augmented state
+    # with the exact history PT-MPO, no truncation: insertions after a few
+    # steps, propagated through later bath interactions
+    m = 9
+    wl = W.random_small_chain(62 + n, n, with_bath_sites=bath_sites, k_cut=k_cut, eps=1e-13)
+    prob, _ = problem_from_workload(wl, form="history", n_steps=m)
+    eng = pt_tebd.Engine(prob)
+    baths = [{"site": b["site"], "coupling_op": b["coupling_op"],
+              "eta": bath.eta_coefficients(b["alpha"], b["wc"], b["temperature"], wl["dt"], k_cut)}
+             for b in wl["baths"]]
+    bf = brute.BruteForce(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths)
+    eng.step(2)
+    bf.step(2)
+    c_gpu_form = eng.correlate(0, SX, n - 1, SZ, 5)
+    c_ref = bf.correlate_multi([(0, 0, SX, "L")], n - 1, SZ, 5)
+    assert np.abs(c_gpu_form - c_ref).max() < 1e-10
+    assert abs(c_ref[0]) > 1e-3 or abs(c_ref[3]) > 1e-3   # a non-trivial correlation
+    for ins in ([(0, n - 1, SY, "R")], [(0, 0, SX, "L"), (2, n - 1, SY, "L")],
+                [(1, 0, SZ, "R"), (3, 0, SX, "L")]):
+        c = eng.correlate_multi(ins, 0, SZ, 3)
+        r = bf.correlate_multi(ins, 0, SZ, 3)
+        assert np.abs(c - r).max() < 1e-10, ins
+    assert eng.mps.step == 2 and bf.step_index == 2
+
+
 def _two_point(eng, sa, a, sb, b):
     rho = eng.reduced_density_matrix()
     n = eng.mps.n_sites
