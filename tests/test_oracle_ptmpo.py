@@ -120,57 +120,6 @@ def oracle_problem_small(wl):
     return prob
 
 
-def test_truncation_rule_examples():
-    # Appendix A.2: the smallest rank whose discarded tail has 2-norm strictly
-    # below eps times the largest singular value
-    sv = np.array([1.0, 1e-3, 1e-8, 1e-9])
-    assert truncation_rank(sv, 1e-7) == 2
-    assert truncation_rank(sv, 1e-4) == 2
-    assert truncation_rank(sv, 1e-2) == 1
-    assert truncation_rank(sv, 0.0) == 4
-    assert truncation_rank(np.array([1.0, 0.0, 0.0]), 0.0) == 1
-    assert truncation_rank(np.array([1.0, 0.5, 0.5, 0.1]), 0.0, chi_max=2) == 1  # tie at the cap
-    assert truncation_rank(np.array([1.0, 0.5, 0.4, 0.1]), 0.0, chi_max=2) == 2
-    # the eps cut is the smallest admissible rank even inside a run of equal
-    # values: the tail beyond rank 3 of [1, 1e-3, 9e-8, 9e-8] is 9e-8 < 1e-7
-    # (beyond rank 2 it is 1.3e-7), so one of the two equal values is kept
-    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8]), 1e-7) == 3
-    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 8e-8]), 1e-7) == 3
-    # the cap (and only the cap) lowers to the start of a degenerate run
-    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8]), 0.0, chi_max=3) == 2
-    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8 - 2e-10]), 0.0, chi_max=3) == 3
-    assert truncation_rank(np.array([1.0, 1e-3, 9e-8, 9e-8 - 5e-11]), 0.0, chi_max=3) == 2
-
-
-def test_truncation_rule_is_the_minimal_admissible_rank():
-    # brute force over every candidate rank: the rule returns the smallest c
-    # with ||sv[c:]||_2 < eps * sv[0] (rank >= 1, zeros never kept), then
-    # min(c, chi_max) unless the cap splits a degenerate pair
-    rng = np.random.default_rng(11)
-    for trial in range(400):
-        n = int(rng.integers(1, 30))
-        sv = np.sort(10.0 ** rng.uniform(-12, 0, size=n))[::-1]
-        if trial % 5 == 0:
-            sv[n // 2:] = 0.0
-        eps = 10.0 ** rng.uniform(-9, -1)
-        npos = int(np.count_nonzero(sv > 0))
-        admissible = [c for c in range(1, npos + 1)
-                      if np.sqrt(np.sum(sv[c:npos] ** 2)) < eps * sv[0] or c == npos]
-        want = min(admissible) if npos else 1
-        assert truncation_rank(sv, eps) == want
-        cap = int(rng.integers(1, n + 1))
-        got = truncation_rank(sv, eps, chi_max=cap)
-        if want <= cap:
-            assert got == want
-        else:
-            assert 1 <= got <= cap
-            # the values kept and dropped at the cap are separated by more
-            # than the degeneracy tolerance, and nothing above it was dropped
-            if got > 1 or sv[0] - sv[1] >= 1e-10 * sv[0]:
-                assert sv[got - 1] - sv[got] >= 1e-10 * sv[0]
-            assert all(sv[c - 1] - sv[c] < 1e-10 * sv[0] for c in range(got + 1, cap + 1))
-
-
 def test_read_out_survives_a_scale_beyond_the_double_range():
     # the chain log-scale and the tensors may each leave the double range
     # (the N = 21 workload reaches log-scale -714 by step 54) while the
