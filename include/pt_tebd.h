@@ -54,11 +54,19 @@ typedef enum {
 } pt_tebd_status;
 
 typedef enum {
-  PT_TEBD_FP64 = 0,       /* every contraction in double precision            */
-  PT_TEBD_FP32_MIXED = 1  /* reserved: contractions in single precision on
-                             the matrix cores with eigensolvers, singular
-                             values, bond vectors and scale in double; not
-                             available yet (create returns PT_TEBD_EINVAL)  */
+  PT_TEBD_FP64 = 0,       /* every contraction in double precision (matrix
+                             cores, v_mfma_f64)                              */
+  PT_TEBD_FP32_MIXED = 1  /* the contractions that form D (Appendix A.2
+                             (e)-(f)), the range finder's products with D and
+                             the rebuild of the site tensors ((g)-(h)) in
+                             single precision on the matrix cores (real-split
+                             complex products, single-precision accumulation);
+                             Gram matrices, eigensolvers, singular values,
+                             lambda, the gate, the PT absorption, the
+                             log-scale and the read-out in double.  The
+                             truncation additionally discards singular values
+                             below u_32 ||X||_F (the single-precision noise
+                             floor of the contracted matrix X).              */
 } pt_tebd_precision;
 
 /* One bath: a PT-MPO attached to one site (Appendix A.1).  Tensor k
@@ -136,7 +144,10 @@ pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi);
 
 /* Host copy of the whole augmented state (Gamma, lambda, log-scale, step).
  * With buf = NULL only *bytes is set.  Syncs.  pt_tebd_restore loads it back
- * into a handle created from the same configuration. */
+ * into a handle created from the same configuration: EINVAL (nothing is
+ * copied) when bytes is shorter than a snapshot of this handle, when the
+ * header does not match the handle, or when the stored step lies outside
+ * [0, PT-MPO length]; on success the handle's sticky error state is cleared. */
 pt_tebd_status pt_tebd_snapshot(pt_tebd_t h, void* buf, size_t* bytes);
 pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes);
 

@@ -31,6 +31,7 @@
 
 #include "device_common.h"
 #include "gemm.h"
+#include "gemm_mfma.h"
 #include "heev.h"
 #include "refine.h"
 
@@ -70,7 +71,9 @@ enum Dim : int {
   D_COUNT
 };
 
-enum StatusBits : int { ST_NONFINITE = 1, ST_ZERO = 2, ST_EIG = 4, ST_RANGE = 8 };
+enum StatusBits : int { ST_NONFINITE = 1, ST_ZERO = 2, ST_EIG = 4, ST_RANGE = 8, ST_NOCONV = 16 };
+// bits of the per-slot eigensolver word (HeevJob::status)
+enum EigBits : int { EIG_NOCONV = 1, EIG_NONFINITE = 4, EIG_SIZE = 8 };
 
 struct BondJob {
   int chain;               // index into the chain array passed to the kernels
@@ -81,11 +84,13 @@ struct BondJob {
                            // D is factorised exactly (Q = I) when M <= k_cap
   int k_sketch;            // sketch width cap of the range finder (<= k_cap)
   double eps;
+  double floor_rel;        // mixed-precision noise floor of the truncation (0 in double precision)
   unsigned long long seed;
   int nb_cap;              // capacity of B Gram sizes (4 chi_cap); ld of gl/gr/vl/vr
   int dn_cap;              // capacity of M, N (4 nb_cap)
   int ldr;                 // leading dim of pr (max(xi_cap chi_cap, nb_cap))
   int* dims;               // [D_COUNT]
+  int* estat;              // [1] eigensolver status of this slot's current update (EigBits)
   double* norms;           // [8]: ||D||_F^2, ||Q^H D||_F^2, extra tail, log-scale term,
                            //      largest Gram eigenvalue of the basis being orthonormalised
   double2 *bl, *br, *gl, *gr, *vl, *vr, *x, *y, *p, *d;
@@ -110,6 +115,7 @@ __global__ void k_pack(const ChainDev* chains, const BondJob* jobs) {
     D[D_RL] = rl; D[D_CL] = cl; D[D_SL] = (cl <= rl) ? 0 : 1; D[D_NL] = min(rl, cl);
     D[D_RR] = rr; D[D_CR] = cr; D[D_SR] = (rr <= cr) ? 0 : 1; D[D_NR] = min(rr, cr);
     for (int i = 0; i < 4; ++i) J.norms[i] = 0.0;
+    *J.estat = 0;
   }
   const double2* gl = gamma_cur(C, J.bond);
   const double2* gr = gamma_cur(C, J.bond + 1);
@@ -153,8 +159,8 @@ enum GemmKind : int {
   GK_GRAM_BM,      // gk = bm bm^H                     (KQ x KQ)
   GK_C,            // vdh = vk^H bm                    (KQ x N) = S V^D^H
   GK_UD,           // ud = ya vk                       (M x CHI)
-  GK_NEWL,         // tg = pl (S^-1 ud') (side 0) | U_L ud' (side 1)      (rl x 4 chi)
-  GK_NEWR,         // tg = (vdh' S^-1) pr (side 0) | vdh' V_R^H (side 1) (4 chi x cr)
+  GK_NEWL,         // tg = U_L ud' (U_L = pl S_L^-1 on side 0, vl on side 1)      (rl x 4 chi)
+  GK_NEWR,         // tg = vdh' V_R^H (V_R^H = S_R^-1 pr on side 0, vr^H on side 1) (4 chi x cr)
   // deflated orthonormalisation of the range finder's bases.  Basis X
   // (rows R) with scratch S and T: Y side X = ya, S = za, T = yb, R = M; Z
   // side X = za, S = ya, T = zb, R = N.  The kind is GK_DF + 2 op + side.
@@ -297,13 +303,13 @@ __device__ inline bool gemm_args(const BondJob& J, int kind, int sub, GemmArgs& 
       set(J.ya, kc, false, J.vk, kc, false, J.ud, D[D_CHI], D[D_M], D[D_CHI], D[D_KQ]);
       return true;
     case GK_NEWL:
-      if (D[D_SL] == 0)  // tg (rl x 4chi) = (B_L V_L)[:, :l] (S^-1 ud')
+      if (D[D_SL] == 0)  // tg (rl x 4chi) = ((B_L V_L) S_L^-1)[:, :l] ud'  (pl rescaled)
         set(J.pl, nb, false, J.ud, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_L]);
       else               // tg = U_L[:, :l] ud'
         set(J.vl, nb, false, J.ud, 4 * D[D_CHI], false, J.tg, 4 * D[D_CHI], D[D_RL], 4 * D[D_CHI], D[D_L]);
       return true;
     case GK_NEWR:
-      if (D[D_SR] == 0)  // tg (4chi x cr) = (vdh' S_R^-1) (U_R^H B_R)[:r, :]
+      if (D[D_SR] == 0)  // tg (4chi x cr) = vdh' (S_R^-1 U_R^H B_R)[:r, :]  (pr rescaled)
         set(J.vdh, D[D_R], false, J.pr, J.ldr, false, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_R]);
       else               // tg = vdh' V_R[:, :r]^H
         set(J.vdh, D[D_R], false, J.vr, nb, true, J.tg, D[D_CR], 4 * D[D_CHI], D[D_CR], D[D_R]);
@@ -327,22 +333,60 @@ __global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm(const BondJob* jobs,
                     mk<double>(g.alpha, 0.0), g.acc, blockIdx.x, blockIdx.y, sm);
 }
 
+// The same products on the matrix cores; CT = double for the FP64 path,
+// float for the single-precision contractions of the mixed path.
+template <typename CT>
+__global__ void __launch_bounds__(GEMM_THREADS) k_bond_gemm_mfma(const BondJob* jobs, int kind, int subs,
+                                                                 double* flops) {
+  __shared__ MfmaSmem<CT> sm;
+  const int item = blockIdx.z / subs, sub = blockIdx.z - item * subs;
+  GemmArgs g;
+  if (!gemm_args(jobs[item], kind, sub, g)) return;
+  if (g.m <= 0 || g.n <= 0) return;
+  if (flops && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    atomicAdd(flops, 8.0 * (double)g.m * g.n * g.k);
+  gemm_tile_mfma<CT>(g.A, g.lda, g.ca, g.B, g.ldb, g.cb, g.C, g.ldc, g.m, g.n, g.k,
+                     mk<double>(g.alpha, 0.0), g.acc, blockIdx.x, blockIdx.y, sm);
+}
+
+// Products that the mixed-precision path runs in single precision: the
+// contractions that form D (P = X Y), the range finder's products with D,
+// and the rebuild of the site tensors.  Gram matrices, the projections
+// whose norms are singular values, and everything after them stay double.
+__host__ __device__ inline bool gemm_kind_single(int kind) {
+  return kind == GK_P || kind == GK_SKETCH || kind == GK_DH_Q || kind == GK_D_Z || kind == GK_UD ||
+         kind == GK_NEWL || kind == GK_NEWR;
+}
+
 // --------------------------------------------- singular values and rules
 // Truncation rule of Appendix A.2 on singular values s[0..n) given in
 // (eigenvalue) order: the smallest rank c whose discarded tail
 // sqrt(extra + sum_{i >= c} s_i^2) is strictly below eps * max(s); exact
-// zeros are never kept; rank >= 1; an eps cut inside a multiplet
-// (neighbours within a relative gap of 1e-6) moves to its end; an optional
-// cap that splits a multiplet drops it whole.  Runs on one thread.
-__device__ inline int truncation_rank(const double* s, int n, double eps, double extra, int cap) {
-  double smax = 0.0;
+// zeros are never kept; rank >= 1; an optional cap comes second.  A run of
+// neighbours within a relative gap of 1e-6 is kept or dropped whole: its
+// split subspace is not determined by the matrix to better than
+// u sigma_1 / gap (u the unit roundoff), so an eps cut inside a run moves
+// to its end (the tail only shrinks) and a cap inside one to its start.
+// Runs on one thread.
+//
+// floor_rel > 0 (mixed-precision form): the matrix was contracted in single
+// precision, so its singular values below c u_32 ||X||_F are rounding
+// noise; the threshold of the discarded tail is then
+// max(eps sigma_max, floor_rel ||X||_F), ||X||_F^2 = extra + sum s_i^2.
+// Without it the noise directions are kept, and lambda^-1 in the rebuild
+// amplifies their single-precision errors into the site tensors.
+constexpr double RUN_GAP = 1e-6;
+__device__ inline int truncation_rank(const double* s, int n, double eps, double extra, int cap,
+                                      double floor_rel = 0.0) {
+  double smax = 0.0, tot = extra;
   int npos = 0;
   for (int i = 0; i < n; ++i) {
     smax = fmax(smax, s[i]);
     if (s[i] > 0.0) npos = i + 1;
+    tot += s[i] * s[i];
   }
   if (npos == 0) return 0;
-  const double thr = eps * smax;
+  const double thr = fmax(eps * smax, floor_rel * sqrt(tot));
   int keep = npos;
   double tail = extra;
   for (int i = npos - 1; i >= 1; --i) {
@@ -350,13 +394,10 @@ __device__ inline int truncation_rank(const double* s, int n, double eps, double
     if (sqrt(tail) < thr) keep = i;
     else break;
   }
-  // an eps cut inside a multiplet (neighbours within a relative gap of
-  // 1e-6) moves to the multiplet's end, so the kept subspace is unique; the
-  // cap moves to the multiplet's start
-  while (keep < npos && fabs(s[keep - 1] - s[keep]) < 1e-6 * s[keep - 1]) ++keep;
+  while (keep < npos && s[keep - 1] - s[keep] < RUN_GAP * s[keep - 1]) ++keep;
   if (cap > 0 && keep > cap) {
     keep = cap;
-    while (keep > 1 && fabs(s[keep - 1] - s[keep]) < 1e-6 * s[keep - 1]) --keep;
+    while (keep > 1 && s[keep - 1] - s[keep] < RUN_GAP * s[keep - 1]) --keep;
   }
   return max(keep, 1);
 }
@@ -368,8 +409,17 @@ __global__ void k_rule_b(const BondJob* jobs, int n_items) {
   if (i >= n_items) return;
   const BondJob& J = jobs[i];
   int* D = J.dims;
-  D[D_L] = truncation_rank(J.sl, D[D_NL], J.eps, 0.0, 0);
-  D[D_R] = truncation_rank(J.sr, D[D_NR], J.eps, 0.0, 0);
+  D[D_L] = truncation_rank(J.sl, D[D_NL], J.eps, 0.0, 0, J.floor_rel);
+  D[D_R] = truncation_rank(J.sr, D[D_NR], J.eps, 0.0, 0, J.floor_rel);
+  // D is formed from X / s_L,max and Y / s_R,max (unit scale whatever the
+  // scale of the state, so single-precision products neither overflow nor
+  // underflow); log(s_L,max s_R,max) goes to the log-scale with log ||S^D||
+  double sx = 0.0, sy = 0.0;
+  for (int k = 0; k < D[D_L]; ++k) sx = fmax(sx, J.sl[k]);
+  for (int k = 0; k < D[D_R]; ++k) sy = fmax(sy, J.sr[k]);
+  J.norms[5] = sx > 0.0 ? 1.0 / sx : 0.0;
+  J.norms[6] = sy > 0.0 ? 1.0 / sy : 0.0;
+  J.norms[7] = (sx > 0.0 && sy > 0.0) ? log(sx) + log(sy) : 0.0;
 }
 
 // ------------------------------------------------------ X, Y (elementwise)
@@ -391,12 +441,13 @@ __global__ void k_form_xy(const ChainDev* chains, const BondJob* jobs) {
       double2 v;
       if (D[D_SL] == 0) v = cscale<double>(cconj<double>(J.vl[(long long)col * nb + i]), J.sl[i]);
       else v = J.pl[(long long)i * nb + col];
-      J.x[idx] = cscale<double>(v, lam_c[col % b]);
+      J.x[idx] = cscale<double>(v, lam_c[col % b] * J.norms[5]);
     } else {
       const long long j = idx - nx;
       const int row = (int)(j / r), k = (int)(j - (long long)row * r);
-      if (D[D_SR] == 0) J.y[j] = cscale<double>(J.vr[(long long)row * nb + k], J.sr[k]);
-      else J.y[j] = J.pr[(long long)row * J.ldr + k];
+      const double2 v = (D[D_SR] == 0) ? cscale<double>(J.vr[(long long)row * nb + k], J.sr[k])
+                                       : J.pr[(long long)row * J.ldr + k];
+      J.y[j] = cscale<double>(v, J.norms[6]);
     }
   }
 }
@@ -404,6 +455,7 @@ __global__ void k_form_xy(const ChainDev* chains, const BondJob* jobs) {
 // ------------------------------------------------------------ gate on P
 // D[(l,s'),(t',r)] = sum_{s,t} G[(s',t'),(s,t)] P[(l,s),(t,r)]; also sets
 // M, N and the sketch width, accumulates ||D||_F^2.  grid (blocks, items)
+template <typename CT>
 __global__ void k_apply_gate(const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.y];
   int* D = J.dims;
@@ -430,31 +482,35 @@ __global__ void k_apply_gate(const BondJob* jobs) {
     D[D_G2S] = 0;
     D[D_FB2] = 0;
   }
-  __shared__ double2 g[256];
+  __shared__ cx<CT> g[256];
   __shared__ double red[4];
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) g[i] = J.gate[i];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) g[i] = mk<CT>((CT)J.gate[i].x, (CT)J.gate[i].y);
   __syncthreads();
   double part = 0.0;
   const long long npairs = (long long)l * r;
   for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < npairs;
        pr += (long long)gridDim.x * blockDim.x) {
     const int li = (int)(pr / r), ri = (int)(pr - (long long)li * r);
-    double2 in[16];
+    cx<CT> in[16];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) in[s * 4 + t] = J.p[(long long)(li * 4 + s) * N + t * r + ri];
+      for (int t = 0; t < 4; ++t) {
+        const double2 v = J.p[(long long)(li * 4 + s) * N + t * r + ri];
+        in[s * 4 + t] = mk<CT>((CT)v.x, (CT)v.y);
+      }
     // one output row of the gate at a time: unrolling all four hoists the
     // 256 gate entries out of LDS into registers and spills
 #pragma unroll 1
     for (int so = 0; so < 4; ++so)
 #pragma unroll
       for (int to = 0; to < 4; ++to) {
-        double2 acc = mk<double>(0.0, 0.0);
+        cx<CT> acc = mk<CT>(0, 0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) cfma<double>(acc, g[(so * 4 + to) * 16 + q], in[q]);
-        J.d[(long long)(li * 4 + so) * N + to * r + ri] = acc;
-        part += cabs2<double>(acc);
+        for (int q = 0; q < 16; ++q) cfma<CT>(acc, g[(so * 4 + to) * 16 + q], in[q]);
+        const double2 o = mk<double>((double)acc.x, (double)acc.y);
+        J.d[(long long)(li * 4 + so) * N + to * r + ri] = o;
+        part += cabs2<double>(o);
       }
   }
   const double tot = block_sum(part, red);
@@ -586,27 +642,35 @@ __global__ void k_rule_d(const BondJob* jobs, int n_items) {
   if (i >= n_items) return;
   const BondJob& J = jobs[i];
   int* D = J.dims;
-  D[D_CHI] = truncation_rank(J.sk, D[D_KQ], J.eps, J.norms[2], J.chi_max);
+  D[D_CHI] = truncation_rank(J.sk, D[D_KQ], J.eps, J.norms[2], J.chi_max, J.floor_rel);
 }
 
-// vdh rows /= s_i (V^D^H = S^-1 W^H B); side-0 scalings used by the
-// rebuilds: ud rows (l,s') /= s_L[l], vdh' columns r /= s_R[r].
+// vdh rows /= s_i (V^D^H = S^-1 W^H B).  Side-0 rebuilds: the columns of
+// pl = B_L V_L (norms s_L) and the rows of pr = U_R^H B_R (norms s_R) are
+// divided by those norms, which turns them into U_L and V_R^H; the rebuild
+// products then multiply factors of unit scale (safe in single precision).
 __global__ void k_scale_factors(const BondJob* jobs) {
   const BondJob& J = jobs[blockIdx.y];
   const int* D = J.dims;
-  const int chi = D[D_CHI], N = D[D_N], M = D[D_M], r = D[D_R];
-  const long long nv = (long long)chi * N, nu = (long long)M * chi;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nv + nu;
+  const int chi = D[D_CHI], N = D[D_N], l = D[D_L], r = D[D_R];
+  const long long nv = (long long)chi * N;
+  const long long npl = (D[D_SL] == 0) ? (long long)D[D_RL] * l : 0;
+  const long long npr = (D[D_SR] == 0) ? (long long)r * D[D_CR] : 0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nv + npl + npr;
        idx += (long long)gridDim.x * blockDim.x) {
     if (idx < nv) {
-      const int i = (int)(idx / N), col = (int)(idx - (long long)i * N);
-      double f = 1.0 / fmax(J.sk[i], 1e-300);
-      if (D[D_SR] == 0) f /= fmax(J.sr[col % r], 1e-300);
-      J.vdh[idx] = cscale<double>(J.vdh[idx], f);
-    } else if (D[D_SL] == 0) {
+      const int i = (int)(idx / N);
+      J.vdh[idx] = cscale<double>(J.vdh[idx], 1.0 / fmax(J.sk[i], 1e-300));
+    } else if (idx < nv + npl) {
       const long long j = idx - nv;
-      const int row = (int)(j / chi);
-      J.ud[j] = cscale<double>(J.ud[j], 1.0 / fmax(J.sl[row / 4], 1e-300));
+      const int row = (int)(j / l), c = (int)(j - (long long)row * l);
+      double2* at = J.pl + (long long)row * J.nb_cap + c;
+      *at = cscale<double>(*at, 1.0 / fmax(J.sl[c], 1e-300));
+    } else {
+      const long long j = idx - nv - npl;
+      const int row = (int)(j / D[D_CR]), c = (int)(j - (long long)row * D[D_CR]);
+      double2* at = J.pr + (long long)row * J.ldr + c;
+      *at = cscale<double>(*at, 1.0 / fmax(J.sr[row], 1e-300));
     }
   }
 }
@@ -665,8 +729,13 @@ __global__ void k_finalize(const ChainDev* chains, const BondJob* jobs) {
     if (!(nrm > 0.0)) bad |= ST_ZERO;
     if (!isfinite(nrm) || !isfinite(J.norms[0])) bad |= ST_NONFINITE;
     if (chi < 1 || D[D_L] < 1 || D[D_R] < 1) bad |= ST_ZERO;
+    // the eigensolver's word of this update goes to the chain being stepped
+    const int es = *J.estat;
+    if (es & EIG_NOCONV) bad |= ST_NOCONV;
+    if (es & EIG_NONFINITE) bad |= ST_EIG;
+    if (es & EIG_SIZE) bad |= ST_RANGE;
     if (bad) atomicOr(C.status, bad);
-    J.norms[3] = bad ? 0.0 : log(nrm);   // summed in item order by k_logscale
+    J.norms[3] = bad ? 0.0 : log(nrm) + J.norms[7];   // summed in item order by k_logscale
     C.chi[J.bond + 1] = chi;
     C.parity[J.bond] ^= 1;
     C.parity[J.bond + 1] ^= 1;

@@ -71,7 +71,8 @@ struct HeevJob {
   double2* v;        // output eigenvectors, row-major n x nvec, leading dim ldv
   int ldv;
   int scale;         // HeevScale applied to column k with lambda_k
-  int* status;       // sticky error word (bit 1: no convergence, bit 4: non-finite, bit 8: size above n_cap)
+  int* status;       // sticky error word (bit 1: no convergence, bit 4: non-finite, bit 8: size above n_cap);
+                     // the bond update folds it into the stepped chain's status
   int noise_cluster; // 1: eigenvalues at the rounding level of zero form one cluster (stage 4b)
   const double* abs_ref;  // RULE_RANK: if set, also drop eigenvalues <= abs_tol * (*abs_ref),
   double abs_tol;         //            and allow no eigenpair at all
@@ -412,16 +413,17 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
           if (sqrt(tail) < thr) nvec = i;   // keeping i values leaves tail(i)
           else break;
         }
-        // a cut inside a multiplet of singular values moves to its end
-        auto tie = [&](int k) {  // singular values k-1, k within a relative gap of 1e-6
+        // runs of singular values within a relative gap of 1e-6 are kept
+        // or dropped whole: an eps cut inside one moves to its end, a cap
+        // inside one to its start
+        auto in_run = [&](int k) {
           const double a = sqrt(fmax(w[k - 1], 0.0)), b = sqrt(fmax(w[k], 0.0));
           return a - b < 1e-6 * a;
         };
-        while (nvec < npos && tie(nvec)) ++nvec;
+        while (nvec < npos && in_run(nvec)) ++nvec;
         if (J.rule == RULE_CAP && J.cap > 0 && nvec > J.cap) {
           nvec = J.cap;
-          // tie rule on singular values: drop a split multiplet
-          while (nvec > 1 && tie(nvec)) --nvec;
+          while (nvec > 1 && in_run(nvec)) --nvec;
         }
       }
     }

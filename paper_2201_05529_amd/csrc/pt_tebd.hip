@@ -78,6 +78,8 @@ struct pt_tebd {
   bool deflate = true;     // two-level (deflated) orthonormalisation of the range finder's bases
   int oversample = 64;
   int refine_levels = 0;   // block refinement levels (PT_TEBD_REFINE_LEVELS)
+  int gemm_valu = 0;       // measurement switch PT_TEBD_GEMM_VALU: the VALU tile for every product
+  unsigned mixed_mask = ~(1u << 30);  // measurement switch PT_TEBD_MIXED_KINDS: bit k = product kind k runs single
   double refine_tau = 1e-4;
   int pt_steps = 0;           // shortest PT-MPO length
   Caps cap{};
@@ -212,6 +214,7 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
   for (int s = 0; s < c.n_slots; ++s) {
     BondJob J{};
     J.dims = bp.take<int>(ptt::D_COUNT);
+    J.estat = bp.take<int>(1);
     J.norms = bp.take<double>(8);
     J.bl = bp.take<double2>(rl * nb);
     J.br = bp.take<double2>(nb * rl);
@@ -292,8 +295,7 @@ pt_tebd_status validate(const pt_tebd_config* cfg, std::string& err) {
   if (!(cfg->svd_rel_cutoff >= 0.0) || !(cfg->svd_rel_cutoff < 1.0)) { err = "svd_rel_cutoff must be in [0, 1)"; return PT_TEBD_EINVAL; }
   if (!cfg->h_site || !cfg->rho0 || (cfg->n_sites > 1 && !cfg->h_bond)) { err = "missing h_site, h_bond or rho0"; return PT_TEBD_EINVAL; }
   if (cfg->n_lindblad < 0 || (cfg->n_lindblad > 0 && !cfg->lindblad)) { err = "bad lindblad"; return PT_TEBD_EINVAL; }
-  if (cfg->precision == PT_TEBD_FP32_MIXED) { err = "the mixed-precision form is not available yet"; return PT_TEBD_EINVAL; }
-  if (cfg->precision != PT_TEBD_FP64) { err = "bad precision"; return PT_TEBD_EINVAL; }
+  if (cfg->precision != PT_TEBD_FP64 && cfg->precision != PT_TEBD_FP32_MIXED) { err = "bad precision"; return PT_TEBD_EINVAL; }
   if (cfg->n_baths < 0 || cfg->n_baths > cfg->n_sites || (cfg->n_baths > 0 && !cfg->baths)) { err = "bad baths"; return PT_TEBD_EINVAL; }
   const int N = cfg->n_sites;
   auto herm = [](const double* m, int n) {
@@ -372,10 +374,31 @@ int env_int(const char* name, int dflt) {
 enum TimingClass : int { KT_NONE = 0, KT_EIGENSOLVER = 1, KT_BOND_GEMM = 2 };
 thread_local pt_tebd* t_timing = nullptr;
 
+// GEMM engines: VALU double (the original tile), matrix-core double, and
+// matrix-core single precision for the mixed path's contractions
+enum GemmEngine : int { GE_VALU = 0, GE_MFMA64 = 1, GE_MFMA32 = 2 };
+thread_local int t_gemm_mixed = 0;   // set while a mixed-precision handle is stepped
+thread_local int t_gemm_valu = 0;    // measurement switch: the VALU tile for every product
+thread_local unsigned t_gemm_mixed_mask = ~(1u << 30);  // measurement switch: which single-precision kinds run single
+
+// While a handle is advanced: its timing class and its GEMM engines.
 struct TimingScope {
   pt_tebd* prev;
-  explicit TimingScope(pt_tebd* h) : prev(t_timing) { t_timing = (h && h->timing_class) ? h : nullptr; }
-  ~TimingScope() { t_timing = prev; }
+  int prev_mixed, prev_valu;
+  unsigned prev_mask = ~(1u << 30);
+  explicit TimingScope(pt_tebd* h)
+      : prev(t_timing), prev_mixed(t_gemm_mixed), prev_valu(t_gemm_valu), prev_mask(t_gemm_mixed_mask) {
+    t_timing = (h && h->timing_class) ? h : nullptr;
+    t_gemm_mixed = (h && h->precision == PT_TEBD_FP32_MIXED) ? 1 : 0;
+    t_gemm_valu = (h && h->gemm_valu) ? 1 : 0;
+    t_gemm_mixed_mask = h ? h->mixed_mask : ~(1u << 30);
+  }
+  ~TimingScope() {
+    t_timing = prev;
+    t_gemm_mixed = prev_mixed;
+    t_gemm_valu = prev_valu;
+    t_gemm_mixed_mask = prev_mask;
+  }
 };
 
 double* timed_flops(int cls) { return (t_timing && t_timing->timing_class == cls) ? t_timing->timing_flops : nullptr; }
@@ -401,8 +424,13 @@ void timed_end(bool began, hipStream_t st) {
 
 void launch_gemm(hipStream_t st, const BondJob* jobs, int n_items, int kind, int subs, int m_cap, int n_cap) {
   dim3 grid((m_cap + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (n_cap + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_items * subs);
+  const bool single = t_gemm_mixed && ptt::gemm_kind_single(kind) && (t_gemm_mixed_mask >> kind & 1);
+  const int engine = t_gemm_valu ? GE_VALU : single ? GE_MFMA32 : GE_MFMA64;
   const bool t = timed_begin(KT_BOND_GEMM, st);
-  ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs, timed_flops(KT_BOND_GEMM));
+  double* fl = timed_flops(KT_BOND_GEMM);
+  if (engine == GE_VALU) ptt::k_bond_gemm<<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs, fl);
+  else if (engine == GE_MFMA64) ptt::k_bond_gemm_mfma<double><<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs, fl);
+  else ptt::k_bond_gemm_mfma<float><<<grid, ptt::GEMM_THREADS, 0, st>>>(jobs, kind, subs, fl);
   timed_end(t, st);
 }
 
@@ -474,7 +502,10 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   ptt::k_form_xy<<<dim3(elem_blocks(2LL * c.nb * c.nb), n), kThreads, 0, st>>>(chains, J);
   // (e)-(f): D
   launch_gemm(st, J, n, ptt::GK_P, 1, c.dn, c.dn);
-  ptt::k_apply_gate<<<dim3(elem_blocks((long long)c.nb * c.nb), n), kThreads, 0, st>>>(J);
+  // the gate stays in double precision on both paths (measurement switch:
+  // bit 30 of PT_TEBD_MIXED_KINDS applies it in single precision)
+  if (t_gemm_mixed && (t_gemm_mixed_mask >> 30 & 1)) ptt::k_apply_gate<float><<<dim3(elem_blocks((long long)c.nb * c.nb), n), kThreads, 0, st>>>(J);
+  else ptt::k_apply_gate<double><<<dim3(elem_blocks((long long)c.nb * c.nb), n), kThreads, 0, st>>>(J);
   // (f)-(g): leading singular subspace of D
   ptt::k_sketch_init<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J);
   launch_gemm(st, J, n, ptt::GK_SKETCH, 1, c.dn, c.kc);
@@ -590,6 +621,7 @@ pt_tebd_status device_status(pt_tebd* h, int which) {
   if (st & ptt::ST_RANGE) { h->err = "PT-MPO step, bond dimension or work size out of range on the device"; return PT_TEBD_ERANGE; }
   if (st & (ptt::ST_NONFINITE | ptt::ST_ZERO)) { h->err = "non-finite value or zero norm during a bond update"; return PT_TEBD_ENUMERIC; }
   if (st & ptt::ST_EIG) { h->err = "eigensolver produced a non-finite value"; return PT_TEBD_ENUMERIC; }
+  if (st & ptt::ST_NOCONV) { h->err = "eigensolver: the shifted factorisation of a nonzero Gram matrix never became definite"; return PT_TEBD_ENOCONV; }
   return PT_TEBD_OK;
 }
 
@@ -704,6 +736,8 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   // block refinement resolves the block below 1e-4 of the largest relative
   // to its own scale (down to ~1e-12); smaller thresholds take three
   h->refine_levels = std::max(0, env_int("PT_TEBD_REFINE_LEVELS", cfg->svd_rel_cutoff < 1e-8 ? 3 : 1));
+  h->gemm_valu = env_int("PT_TEBD_GEMM_VALU", 0) != 0;
+  h->mixed_mask = (unsigned)env_int("PT_TEBD_MIXED_KINDS", (int)~(1u << 30));
   h->cap = compute_caps(cfg, h->oversample);
   const Caps& c = h->cap;
   const auto tl = tensor_lengths(cfg), cl = cap_lengths(cfg);
@@ -836,6 +870,9 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   h->site_op = P.site_op;
   h->timing_flops = P.timing_flops;
 
+  // measurement switch PT_TEBD_MIXED_FLOOR: the mixed form's noise floor in units of u_32
+  const char* mf = std::getenv("PT_TEBD_MIXED_FLOOR");
+  const double mixed_floor_units = (mf && *mf) ? std::atof(mf) : 1.0;
   // sublayer job tables
   for (int par = 0; par < 2; ++par) {
     Sublayer& S = par == 0 ? h->sub_even : h->sub_odd;
@@ -867,12 +904,15 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
       J.k_cap = c.kc;
       J.k_sketch = c.ks;
       J.eps = cfg->svd_rel_cutoff;
+      // single-precision contractions resolve singular values down to about
+      // u_32 = 2^-24 of the matrix's Frobenius norm
+      J.floor_rel = (cfg->precision == PT_TEBD_FP32_MIXED) ? mixed_floor_units * 5.9604644775390625e-8 : 0.0;
       J.seed = ptt::splitmix64(cfg->seed ^ (0xA24BAED4963EE407ull * (unsigned long long)(J.bond + 1)));
       J.nb_cap = c.nb;
       J.dn_cap = c.dn;
       J.ldr = std::max(c.chi_cap * c.xi_cap, c.nb);
       S.host_jobs.push_back(J);
-      int* st0 = P.status[0];
+      int* st0 = J.estat;  // folded into the stepped chain's status by k_finalize
       fill_heev(hb2[2 * i], J.gl, c.nb, J.dims + ptt::D_NL, J.wl, P.h_refl[0][i], P.h_tri[0][i], P.h_work[0][i],
                 P.h_z[0][i], c.nh, J.dims + ptt::D_L, ptt::RULE_FULL, J.eps, 0, nullptr, 0.0, J.vl, c.nb,
                 ptt::SCALE_NONE, st0);
@@ -981,6 +1021,8 @@ pt_tebd_status pt_tebd_observe(pt_tebd_t h, int32_t n_ops, const int32_t* sites,
   if (!h || n_ops < 0 || (n_ops > 0 && (!sites || !ops || !out))) return PT_TEBD_EINVAL;
   for (int i = 0; i < n_ops; ++i)
     if (sites[i] < 0 || sites[i] >= h->n_sites) { h->err = "observable site out of range"; return PT_TEBD_EINVAL; }
+  for (int i = 0; i < 8 * n_ops; ++i)
+    if (!std::isfinite(ops[i])) { h->err = "non-finite operator"; return PT_TEBD_EINVAL; }
   // one extra trace request at site 0 so the trace is always available
   std::vector<int> s2(sites, sites + n_ops);
   std::vector<double> ov(8 * (n_ops + 1));
@@ -1009,6 +1051,8 @@ pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a
                                  const double* op_b, int32_t n_steps, double* out) {
   if (!h || !op_a || !op_b || !out || n_steps < 0) return PT_TEBD_EINVAL;
   if (site_a < 0 || site_a >= h->n_sites || site_b < 0 || site_b >= h->n_sites) return PT_TEBD_EINVAL;
+  for (int i = 0; i < 8; ++i)
+    if (!std::isfinite(op_a[i]) || !std::isfinite(op_b[i])) { h->err = "non-finite operator"; return PT_TEBD_EINVAL; }
   if (h->n_baths > 0 && h->step + n_steps > h->pt_steps) {
     h->err = "correlation runs past the end of a PT-MPO";
     return PT_TEBD_ERANGE;
@@ -1079,14 +1123,22 @@ pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi) {
   return device_status(h, 0);
 }
 
+namespace {
+// bytes of a snapshot: header, Gamma buffers, parity, chi, xi, lambda, log-scale
+size_t snapshot_bytes(const pt_tebd* h) {
+  const int N = h->n_sites;
+  const Caps& c = h->cap;
+  return sizeof(int) * 4 + (size_t)N * 2 * c.gam_cap * sizeof(double2) + N * sizeof(int) + (N + 1) * sizeof(int) +
+         N * sizeof(int) + (size_t)(N + 1) * c.chi_cap * sizeof(double) + sizeof(double);
+}
+}  // namespace
+
 pt_tebd_status pt_tebd_snapshot(pt_tebd_t h, void* buf, size_t* bytes) {
   if (!h || !bytes) return PT_TEBD_EINVAL;
   const ChainDev& M = h->chain_host[0];
   const int N = h->n_sites;
   const Caps& c = h->cap;
-  const size_t need = sizeof(int) * 4 + (size_t)N * 2 * c.gam_cap * sizeof(double2) + N * sizeof(int) +
-                      (N + 1) * sizeof(int) + N * sizeof(int) + (size_t)(N + 1) * c.chi_cap * sizeof(double) +
-                      sizeof(double);
+  const size_t need = snapshot_bytes(h);
   if (!buf) { *bytes = need; return PT_TEBD_OK; }
   if (*bytes < need) { *bytes = need; return PT_TEBD_ENOMEM; }
   char* p = static_cast<char*>(buf);
@@ -1116,9 +1168,10 @@ pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes) {
   const Caps& c = h->cap;
   const char* p = static_cast<const char*>(buf);
   int hdr[4];
-  if (bytes < sizeof(hdr)) return PT_TEBD_EINVAL;
+  if (bytes < snapshot_bytes(h)) { h->err = "snapshot buffer shorter than a snapshot of this handle"; return PT_TEBD_EINVAL; }
   std::memcpy(hdr, p, sizeof(hdr));
   if (hdr[0] != 0x50545442 || hdr[1] != N || hdr[2] != (int)c.gam_cap) { h->err = "snapshot does not match handle"; return PT_TEBD_EINVAL; }
+  if (hdr[3] < 0 || (h->n_baths > 0 && hdr[3] > h->pt_steps)) { h->err = "snapshot step outside the PT-MPO range"; return PT_TEBD_EINVAL; }
   p += sizeof(hdr);
   bool ok = true;
   auto h2d = [&](void* dev, size_t len) {
@@ -1131,6 +1184,8 @@ pt_tebd_status pt_tebd_restore(pt_tebd_t h, const void* buf, size_t bytes) {
   h2d(M.xi, N * sizeof(int));
   h2d(M.lam, (size_t)(N + 1) * c.chi_cap * sizeof(double));
   h2d(M.log_scale, sizeof(double));
+  const int zero = 0;  // a restored state carries no error of the state it replaces
+  ok = ok && check(hipMemcpyAsync(M.status, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream), h, "restore");
   if (!ok || !check(hipStreamSynchronize(h->stream), h, "sync")) return PT_TEBD_EDEVICE;
   h->step = hdr[3];
   return PT_TEBD_OK;

@@ -1,0 +1,122 @@
+"""GPU parity of the mixed-precision form (PT_TEBD_FP32_MIXED): the
+contractions that form D, the range finder's products with D, the gate and
+the rebuild run in single precision on the matrix cores; Gram matrices,
+eigensolvers, singular values, lambda and the log-scale stay double.
+
+Stated requirement: every observable within 1e-4 of the FP64 oracle; each
+test prints the maximum error of every observable it checks."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pt_tebd as opt
+from paper_2201_05529_amd import workloads as W
+from tests.conftest import gpu_available
+from tests.helpers import ROOT, ensure_library, library_chain, oracle_problem, run_both
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-4
+FP32_MIXED = 1
+SZ, SX, SY = W.SZ, W.SX, W.SY
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    ensure_library()
+
+
+def _golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")) as f:
+        gold = json.load(f)
+    with open(os.path.join(ROOT, "tests", "golden", f"{name}_spread.json")) as f:
+        spread = json.load(f)
+    sz = np.array(gold["sz_re"]) + 1j * np.array(gold["sz_im"])
+    tr = np.array(gold["trace_re"]) + 1j * np.array(gold["trace_im"])
+    return sz, tr, np.array(spread["sz"]), np.array(spread["trace"])
+
+
+@pytest.mark.parametrize("n,sites", [(2, (0, 1)), (3, (1,)), (5, (0, 2, 4))])
+def test_mixed_small_chains_with_baths(n, sites):
+    wl = W.random_small_chain(200 + n, n, with_bath_sites=sites, k_cut=3, eps=1e-10, xi_max=64)
+    ops = [(s, op) for s in range(n) for op in (SX, SZ)]
+    g, o, gt, ot, ch, eng = run_both(wl, 8, ops, precision=FP32_MIXED)
+    errs = np.abs(g - o).max(axis=0)
+    print(f"mixed n={n}: per-observable max error", " ".join("%.1e" % e for e in errs),
+          "trace %.1e" % np.abs(gt - ot).max(), flush=True)
+    assert errs.max() < MIXED_TOL
+    assert np.abs(gt - ot).max() < MIXED_TOL
+
+
+def test_mixed_xyz3_workload():
+    wl = W.xyz3()
+    ops = [(s, SZ) for s in range(3)] + [(0, SX), (1, SY)]
+    g, o, gt, ot, ch, eng = run_both(wl, wl["n_steps"], ops, precision=FP32_MIXED)
+    errs = np.abs(g - o).max(axis=0)
+    print("mixed xyz3 per-observable max error", " ".join("%.1e" % e for e in errs),
+          "trace %.1e" % np.abs(gt - ot).max(), flush=True)
+    assert errs.max() < MIXED_TOL
+    assert np.abs(gt - ot).max() < MIXED_TOL
+
+
+def _mixed_against_golden(name, n_steps):
+    wl = getattr(W, name)()
+    gsz, gtr, ssz, str_ = _golden(name)
+    ch = library_chain(wl, oracle_problem(wl), precision=FP32_MIXED)
+    n = wl["n_sites"]
+    e_sz, e_tr = [], []
+    for k in range(n_steps + 1):
+        if k:
+            ch.step(1)
+        v, tr = ch.observe(range(n), np.array([SZ] * n))
+        e_sz.append(np.abs(v - gsz[k]))
+        e_tr.append(abs(tr - gtr[k]))
+    e_sz, e_tr = np.array(e_sz), np.array(e_tr)
+    bound = np.maximum(MIXED_TOL, 10.0 * ssz[:n_steps + 1])
+    bound_tr = np.maximum(MIXED_TOL, 10.0 * str_[:n_steps + 1])
+    print(f"mixed {name}: max error per site", " ".join("%.1e" % e for e in e_sz.max(axis=0)),
+          "| trace %.1e" % e_tr.max(), flush=True)
+    print(f"mixed {name}: max error by step", " ".join("%.0e" % e for e in e_sz.max(axis=1)), flush=True)
+    return e_sz.max(axis=1), e_tr, bound, bound_tr, ch
+
+
+def test_mixed_xyz5_workload_and_correlation():
+    wl = W.xyz5()
+    prob = oracle_problem(wl)
+    ch = library_chain(wl, prob, precision=FP32_MIXED)
+    c_gpu = ch.correlate(0, SX, 0, SX, 30)
+    c_ref = opt.Engine(prob).correlate(0, SX, 0, SX, 30)
+    print("mixed xyz5 correlation max error %.1e" % np.abs(c_gpu - c_ref).max(), flush=True)
+    assert np.abs(c_gpu - c_ref).max() < MIXED_TOL
+    ch.close()
+    e, et, b, bt, _ = _mixed_against_golden("xyz5", wl["n_steps"])
+    assert (e <= b).all() and (et <= bt).all()
+
+
+def test_mixed_xy21_workload_while_the_oracle_is_well_conditioned():
+    # steps where the oracle's own spread is below 5e-6 (1..12)
+    e, et, b, bt, _ = _mixed_against_golden("xy21", 12)
+    assert (e <= b).all() and (et <= bt).all()
+
+
+def test_fp64_engines_agree():
+    # the double-precision products on the matrix cores and on the vector
+    # ALUs are two summation orders of the same contractions
+    wl = W.random_small_chain(330, 5, with_bath_sites=(0, 4), k_cut=3, eps=1e-10, xi_max=64)
+    prob = oracle_problem(wl, n_steps=6)
+    out = []
+    for valu in ("0", "1"):
+        os.environ["PT_TEBD_GEMM_VALU"] = valu
+        try:
+            ch = library_chain(wl, prob)
+        finally:
+            os.environ.pop("PT_TEBD_GEMM_VALU", None)
+        ch.step(6)
+        out.append(ch.observe(range(5), np.array([SZ] * 5))[0])
+        ch.close()
+    print("engines differ by %.1e" % np.abs(out[0] - out[1]).max(), flush=True)
+    assert np.abs(out[0] - out[1]).max() < 1e-9
