@@ -203,6 +203,28 @@ pt_tebd_status pt_bath_eta(double alpha, double wc, int32_t cutoff_kind, double 
  * pt_tebd_create built; exposed for testing.  Host-side, no sync. */
 pt_tebd_status pt_tebd_gate(pt_tebd_t h, int32_t bond, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * Hermitian eigensolver of the truncated SVDs with no allocation at all.
+ * n x n complex Hermitian a_dev (row-major, interleaved (re, im), n <= 256,
+ * caller-owned device memory, not modified), rule as pt_test_heev (0 every
+ * positive eigenvalue, 1 the eps rule on sqrt(eigenvalues), 2 the eps rule
+ * plus the cap, 3 numerical rank lambda_k > eps lambda_0, 4 every
+ * eigenpair).  Outputs, all caller-owned device memory: w_dev [n]
+ * eigenvalues (descending), v_dev [n][n] complex with the selected vectors
+ * in columns 0..nvec-1 (the other columns are left as they were),
+ * nvec_dev [1], status_dev [1] (the eigensolver's error word, 0 = OK).
+ * Every other buffer lives in one static device array of the library
+ * (about 6.6 MB per GPU, held until the process ends), so the call makes no
+ * hipMalloc, hipFree or allocating library call; it only enqueues kernels
+ * on hip_stream (NULL = default stream) and returns without synchronising.
+ * Calls that overlap on one GPU share that array and race: serialise them
+ * (one stream, or events).  EINVAL for n outside [1, 256], a bad rule or a
+ * null pointer; EDEVICE if a launch fails. */
+pt_tebd_status pt_heev_noalloc(int32_t n, const double* a_dev, int32_t rule, double eps, int32_t cap,
+                               double* w_dev, double* v_dev, int32_t* nvec_dev, int32_t* status_dev,
+                               void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,7 @@ def lib():
         L.pt_bath_eta.argtypes = [dbl, dbl, i32, dbl, dbl, i32, dp]
         L.pt_mpo_build_ohmic.argtypes = [dbl, dbl, i32, dbl, dbl, i32, i32, dbl, i32, dp, i32, ctypes.POINTER(Bath)]
         L.pt_mpo_free.argtypes = [ctypes.POINTER(Bath)]
+        L.pt_heev_noalloc.argtypes = [i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
         L.pt_mpo_free.restype = None
         for name in ("pt_tebd_workspace_size", "pt_tebd_create", "pt_tebd_step", "pt_tebd_observe",
                      "pt_tebd_correlate", "pt_tebd_bond_dims", "pt_tebd_snapshot", "pt_tebd_restore",
@@ -286,3 +287,27 @@ def step_many(chains, n_steps):
     st = lib().pt_tebd_step_many(arr, len(chains), n_steps)
     if st != 0:
         raise PtTebdError(st, "step_many")
+
+
+def heev_noalloc(a, rule=4, eps=0.0, cap=0, stream=None):
+    """pt_heev_noalloc on a complex Hermitian n x n matrix (NumPy): device
+    buffers for the input and outputs come from torch, the eigensolver's
+    scratch from the library's static device array.  Returns (w, v, nvec,
+    status) after synchronising the stream."""
+    import torch
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    n = a.shape[0]
+    dev = torch.device("cuda")
+    a_d = torch.from_numpy(a.view(np.float64).reshape(-1).copy()).to(dev)
+    w_d = torch.zeros(n, dtype=torch.float64, device=dev)
+    v_d = torch.zeros(2 * n * n, dtype=torch.float64, device=dev)
+    nvec_d = torch.zeros(1, dtype=torch.int32, device=dev)
+    stat_d = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().pt_heev_noalloc(n, a_d.data_ptr(), int(rule), float(eps), int(cap), w_d.data_ptr(), v_d.data_ptr(),
+                               nvec_d.data_ptr(), stat_d.data_ptr(), ctypes.c_void_p(s.cuda_stream))
+    if st != 0:
+        raise PtTebdError(st, "heev_noalloc")
+    s.synchronize()
+    v = v_d.cpu().numpy().view(np.complex128).reshape(n, n)
+    return w_d.cpu().numpy(), v, int(nvec_d.cpu().item()), int(stat_d.cpu().item())

@@ -1394,3 +1394,98 @@ extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule,
   hipFree(dextra); hipFree(dn); hipFree(dnvec); hipFree(dstat); hipFree(djob);
   return st;
 }
+
+// ------------------------------------------------------- no-alloc variant
+// pt_heev_noalloc: the eigensolver of pt_test_heev on caller-owned device
+// buffers, with every other buffer carved out of one file-scope device
+// array.  Host code never passes the array's name to a kernel: the device
+// address of each GPU's copy is taken once per device with
+// hipGetSymbolAddress and kept.
+namespace {
+constexpr int NOALLOC_NMAX = 256;
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t NOALLOC_BYTES =
+    align256(sizeof(HeevJob)) + align256(4 * sizeof(int)) + align256(sizeof(double)) +
+    2 * align256((size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double2)) +  // matrix copy, reflectors
+    align256(6 * (size_t)NOALLOC_NMAX * sizeof(double)) +                  // tridiagonal
+    align256(8 * (size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double)) +   // inverse-iteration work
+    align256((size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double));         // tridiagonal eigenvectors
+}  // namespace
+
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's scratch (set up once per device)
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// scratch layout and the zeroed / copied inputs of one call
+__global__ void k_noalloc_setup(char* base, int n, const double2* a_in, int rule, double eps, int cap, double* w,
+                                double2* v) {
+  size_t off = 0;
+  auto take = [&](size_t b) { char* p = base + off; off += align256(b); return p; };
+  HeevJob* job = reinterpret_cast<HeevJob*>(take(sizeof(HeevJob)));
+  int* ints = reinterpret_cast<int*>(take(4 * sizeof(int)));            // n, nvec, status, pad
+  double* extra = reinterpret_cast<double*>(take(sizeof(double)));
+  double2* a = reinterpret_cast<double2*>(take((size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double2)));
+  double2* refl = reinterpret_cast<double2*>(take((size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double2)));
+  double* tri = reinterpret_cast<double*>(take(6 * (size_t)NOALLOC_NMAX * sizeof(double)));
+  double* work = reinterpret_cast<double*>(take(8 * (size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double)));
+  double* z = reinterpret_cast<double*>(take((size_t)NOALLOC_NMAX * NOALLOC_NMAX * sizeof(double)));
+  const long long tot = (long long)n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x)
+    a[i] = a_in[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ints[0] = n;
+    ints[1] = 0;
+    ints[2] = 0;
+    *extra = 0.0;
+    HeevJob J{};
+    J.a = a; J.lda = n; J.n_ptr = ints; J.refl = refl; J.tri = tri; J.work = work; J.z = z;
+    J.n_cap = n; J.nvec_out = ints + 1; J.rule = rule; J.eps = eps; J.cap = cap; J.extra_tail = extra;
+    J.rank_tol = eps; J.v = v; J.ldv = n; J.scale = ptt::SCALE_NONE; J.status = ints + 2;
+    J.noise_cluster = 1; J.abs_ref = nullptr; J.abs_tol = 0.0; J.w = w;
+    *job = J;
+  }
+}
+
+// number of selected vectors and the eigensolver's status word, to the caller
+__global__ void k_noalloc_finish(const char* base, int* nvec_out, int* status_out) {
+  const int* ints = reinterpret_cast<const int*>(base + align256(sizeof(HeevJob)));
+  *nvec_out = ints[1];
+  *status_out = ints[2];
+}
+}  // namespace
+
+extern "C" pt_tebd_status pt_heev_noalloc(int32_t n, const double* a_dev, int32_t rule, double eps, int32_t cap,
+                                          double* w_dev, double* v_dev, int32_t* nvec_dev, int32_t* status_dev,
+                                          void* hip_stream) {
+  if (n < 1 || n > NOALLOC_NMAX || !a_dev || !w_dev || !v_dev || !nvec_dev || !status_dev) return PT_TEBD_EINVAL;
+  if (rule < 0 || rule > 4) return PT_TEBD_EINVAL;
+  void* base = nullptr;
+  if (scratch_address(&base) != hipSuccess) return PT_TEBD_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int r = rule == 0 ? ptt::RULE_ALL : rule == 1 ? ptt::RULE_EPS : rule == 2 ? ptt::RULE_CAP
+              : rule == 3 ? ptt::RULE_RANK : ptt::RULE_FULL;
+  char* b = static_cast<char*>(base);
+  k_noalloc_setup<<<elem_blocks((long long)n * n), kThreads, 0, st>>>(
+      b, n, reinterpret_cast<const double2*>(a_dev), r, eps, cap, w_dev, reinterpret_cast<double2*>(v_dev));
+  launch_heev(st, reinterpret_cast<const HeevJob*>(b), 1, n);
+  k_noalloc_finish<<<1, 1, 0, st>>>(b, nvec_dev, status_dev);
+  return hipGetLastError() == hipSuccess ? PT_TEBD_OK : PT_TEBD_EDEVICE;
+}
