@@ -158,10 +158,35 @@ int32_t pt_tebd_current_step(pt_tebd_t h);
 const char* pt_tebd_last_error(pt_tebd_t h);
 void pt_tebd_destroy(pt_tebd_t h);
 
-/* Advance n handles by n_steps time steps each, handle after handle, each
- * on its own stream (the bonds of one sublayer of one handle share one set
- * of batched launches; launches are not yet shared across handles).
- * Returns the first failing handle's status. */
+/* Batches: many chains advanced together (the bond updates of a sublayer
+ * are independent, Sec. II.B and Appendix A.2, across chains as within
+ * one).  Each kernel of a sublayer runs once over the bond updates of every
+ * chain of the batch, the PT absorption once over every (chain, bath) pair,
+ * and one time step is captured in a HIP graph on first use and replayed.
+ * The handles must share one stream (not the NULL stream for the graph; on
+ * the NULL stream the launches are issued directly), the precision and the
+ * truncation settings, and have at least two sites; chains may differ in
+ * length, bond caps and PT-MPOs, and may be at different steps.  The batch
+ * keeps pointers to the handles: destroy it before any of them.  While a
+ * batch exists, pt_tebd_step on a member (or a restore) is allowed; the
+ * batch reads each handle's current step when it starts stepping.
+ * pt_tebd_batch_workspace_size gives the device bytes of the batch's job
+ * tables; the caller owns that workspace, which must outlive the batch. */
+typedef struct pt_tebd_batch* pt_tebd_batch_t;
+pt_tebd_status pt_tebd_batch_workspace_size(pt_tebd_t* hs, int32_t n, size_t* bytes);
+pt_tebd_status pt_tebd_batch_create(pt_tebd_t* hs, int32_t n, void* dev_workspace, size_t bytes,
+                                    pt_tebd_batch_t* out);
+/* Enqueue n_steps time steps of every chain (asynchronous; ERANGE if a chain
+ * would pass the end of its PT-MPO, nothing enqueued then).  Device-side
+ * errors are sticky per chain and reported by that handle's next syncing
+ * call. */
+pt_tebd_status pt_tebd_batch_step(pt_tebd_batch_t b, int32_t n_steps);
+const char* pt_tebd_batch_last_error(pt_tebd_batch_t b);  /* NULL: last failed batch_create */
+void pt_tebd_batch_destroy(pt_tebd_batch_t b);
+
+/* Advance n handles by n_steps time steps each as one batch (above), with
+ * the batch's job tables in device memory allocated and freed by the call
+ * (hipMalloc); synchronises before returning. */
 pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps);
 
 /* Measurement support (not part of the method).  pt_tebd_kernel_timing

@@ -79,6 +79,13 @@ def lib():
         L.pt_mpo_build_ohmic.argtypes = [dbl, dbl, i32, dbl, dbl, i32, i32, dbl, i32, dp, i32, ctypes.POINTER(Bath)]
         L.pt_mpo_free.argtypes = [ctypes.POINTER(Bath)]
         L.pt_heev_noalloc.argtypes = [i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
+        L.pt_tebd_batch_workspace_size.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.pt_tebd_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.pt_tebd_batch_step.argtypes = [vp, i32]
+        L.pt_tebd_batch_last_error.argtypes = [vp]
+        L.pt_tebd_batch_last_error.restype = ctypes.c_char_p
+        L.pt_tebd_batch_destroy.argtypes = [vp]
+        L.pt_tebd_batch_destroy.restype = None
         L.pt_mpo_free.restype = None
         for name in ("pt_tebd_workspace_size", "pt_tebd_create", "pt_tebd_step", "pt_tebd_observe",
                      "pt_tebd_correlate", "pt_tebd_bond_dims", "pt_tebd_snapshot", "pt_tebd_restore",
@@ -273,6 +280,46 @@ class Chain:
     def close(self):
         if getattr(self, "handle", None):
             lib().pt_tebd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Chains advanced together (pt_tebd_batch_*): one launch per kernel of a
+    sublayer over every chain, one step captured in a HIP graph.  The chains
+    must share one stream; the batch's job tables live in a torch tensor."""
+
+    def __init__(self, chains):
+        import torch
+        L = lib()
+        self.chains = list(chains)
+        arr = (ctypes.c_void_p * len(self.chains))(*[c.handle for c in self.chains])
+        self._arr = arr
+        size = ctypes.c_size_t()
+        st = L.pt_tebd_batch_workspace_size(arr, len(self.chains), ctypes.byref(size))
+        if st != 0:
+            raise PtTebdError(st, "pt_tebd_batch_workspace_size: " + L.pt_tebd_batch_last_error(None).decode())
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.chains[0].workspace.device)
+        handle = ctypes.c_void_p()
+        st = L.pt_tebd_batch_create(arr, len(self.chains), ctypes.c_void_p(self.workspace.data_ptr()), size.value,
+                                    ctypes.byref(handle))
+        if st != 0:
+            raise PtTebdError(st, "pt_tebd_batch_create: " + L.pt_tebd_batch_last_error(None).decode())
+        self.handle = handle
+
+    def step(self, n=1):
+        st = lib().pt_tebd_batch_step(self.handle, int(n))
+        if st != 0:
+            raise PtTebdError(st, "batch step: " + lib().pt_tebd_batch_last_error(self.handle).decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pt_tebd_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -18,10 +18,9 @@ struct BathDev {
 
 // Gamma_n[a,s,e',b] = sum_e P_k[e,e',s] Gamma_n[a,s,e,b]            (diagonal)
 //                   = sum_{e,s_in} P_k[e,e',s,s_in] Gamma_n[a,s_in,e,b] (dense)
-// grid (blocks, n_baths).  `k` is the 1-based step index.
-__global__ void k_pt_absorb(const ChainDev* chain, const BathDev* baths, int k) {
-  const BathDev& B = baths[blockIdx.y];
-  const ChainDev& C = *chain;
+// for one bath of one chain, by the blocks of the x dimension.  `k` is the
+// 1-based step index.
+__device__ inline void pt_absorb_one(const ChainDev& C, const BathDev& B, int k) {
   const int site = B.site;
   if (k < 1 || k > B.n_steps) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(C.status, ST_RANGE);
@@ -59,15 +58,51 @@ __global__ void k_pt_absorb(const ChainDev* chain, const BathDev* baths, int k) 
   }
 }
 
-// after k_pt_absorb: new augmented dims and buffer swap.  grid 1, threads >= n_baths
-__global__ void k_pt_commit(const ChainDev* chain, const BathDev* baths, int n_baths, int k) {
-  const int i = threadIdx.x;
-  if (i >= n_baths) return;
-  const BathDev& B = baths[i];
-  const ChainDev& C = *chain;
+// grid (blocks, n_baths) on one chain
+__global__ void k_pt_absorb(const ChainDev* chain, const BathDev* baths, int k) {
+  pt_absorb_one(*chain, baths[blockIdx.y], k);
+}
+
+// after the absorption: new augmented dim and buffer swap of one bath site
+__device__ inline void pt_commit_one(const ChainDev& C, const BathDev& B, int k) {
   if (k < 1 || k > B.n_steps || C.xi[B.site] != B.dims[k - 1]) return;
   C.xi[B.site] = B.dims[k];
   C.parity[B.site] ^= 1;
+}
+
+// grid 1, threads >= n_baths
+__global__ void k_pt_commit(const ChainDev* chain, const BathDev* baths, int n_baths, int k) {
+  const int i = threadIdx.x;
+  if (i >= n_baths) return;
+  pt_commit_one(*chain, baths[i], k);
+}
+
+// Batched form over many chains: one work item per (chain, bath); the step
+// index of chain c is kstep[c] + 1, read on the device, so the launch is the
+// same at every step (a captured graph replays it).
+struct BathRef {
+  int chain, pad;
+  const BathDev* bath;
+};
+
+// grid (blocks, n_refs)
+__global__ void k_pt_absorb_batch(const ChainDev* chains, const BathRef* refs, const int* kstep) {
+  const BathRef& R = refs[blockIdx.y];
+  pt_absorb_one(chains[R.chain], *R.bath, kstep[R.chain] + 1);
+}
+
+// one thread per reference
+__global__ void k_pt_commit_batch(const ChainDev* chains, const BathRef* refs, int n_refs, const int* kstep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_refs) return;
+  const BathRef& R = refs[i];
+  pt_commit_one(chains[R.chain], *R.bath, kstep[R.chain] + 1);
+}
+
+// end of a batched step: every chain's step counter advances
+__global__ void k_advance_steps(int* kstep, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) kstep[i] += 1;
 }
 
 // Gamma_i[a,s,e,b] <- sum_{s''} op[s,s''] Gamma_i[a,s'',e,b] (in place; one

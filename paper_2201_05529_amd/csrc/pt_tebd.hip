@@ -63,6 +63,18 @@ struct Caps {
   long long gam_cap;
 };
 
+// What a sublayer's launch sequence needs besides its job tables: the
+// stream, the capacities that size the grids (the largest over the chains
+// of a batch) and the range finder's and refinement's settings.
+struct Exec {
+  hipStream_t stream;
+  Caps cap;
+  int power_iters;
+  bool cholqr, deflate;
+  int refine_levels;
+  double refine_tau;
+};
+
 }  // namespace
 
 struct pt_tebd {
@@ -462,14 +474,18 @@ void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap, int
 
 int elem_blocks(long long n);
 
+Exec exec_of(const pt_tebd* h) {
+  return Exec{h->stream, h->cap, h->power_iters, h->cholqr, h->deflate, h->refine_levels, h->refine_tau};
+}
+
 // levels of block refinement of Gram-based singular values (refine.h)
-void run_refine(pt_tebd* h, const ptt::RefineJob* R, const HeevJob* H, int n_jobs, int m_cap, int n_cap,
+void run_refine(const Exec& x, const ptt::RefineJob* R, const HeevJob* H, int n_jobs, int m_cap, int n_cap,
                 int nh) {
-  hipStream_t st = h->stream;
+  hipStream_t st = x.stream;
   const dim3 gnorm((nh + kThreads / 64 - 1) / (kThreads / 64), n_jobs);
   ptt::k_ref_norms<<<gnorm, kThreads, 0, st>>>(R);
-  for (int level = 0; level < h->refine_levels; ++level) {
-    ptt::k_ref_select<<<(n_jobs + 63) / 64, 64, 0, st>>>(R, n_jobs, h->refine_tau, level);
+  for (int level = 0; level < x.refine_levels; ++level) {
+    ptt::k_ref_select<<<(n_jobs + 63) / 64, 64, 0, st>>>(R, n_jobs, x.refine_tau, level);
     dim3 gg((nh + ptt::GEMM_BM - 1) / ptt::GEMM_BM, (nh + ptt::GEMM_BN - 1) / ptt::GEMM_BN, n_jobs);
     ptt::k_ref_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(R, ptt::RK_GRAM);
     launch_heev(st, H, n_jobs, nh);
@@ -484,11 +500,11 @@ void run_refine(pt_tebd* h, const ptt::RefineJob* R, const HeevJob* H, int n_job
 
 int elem_blocks(long long n) { return (int)std::min<long long>(std::max<long long>((n + kThreads - 1) / kThreads, 1), 1024); }
 
-void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
+void run_sublayer(const Exec& x, const Sublayer& S, const ChainDev* chains) {
   const int n = (int)S.bonds.size();
   if (n == 0) return;
-  const Caps& c = h->cap;
-  hipStream_t st = h->stream;
+  const Caps& c = x.cap;
+  hipStream_t st = x.stream;
   const long long rl = (long long)c.chi_cap * c.xi_cap;
   const int wide = (int)std::max<long long>(rl, c.nb);
   const BondJob* J = S.jobs;
@@ -497,7 +513,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   launch_gemm(st, J, n, ptt::GK_GRAM_B, 2, c.nb, c.nb);
   launch_heev(st, S.heev_b, 2 * n, c.nh);
   launch_gemm(st, J, n, ptt::GK_PROD_B, 2, wide, wide);
-  run_refine(h, S.ref_b, S.heev_ref_b, 2 * n, wide, wide, c.nb);
+  run_refine(x, S.ref_b, S.heev_ref_b, 2 * n, wide, wide, c.nb);
   ptt::k_rule_b<<<(n + 63) / 64, 64, 0, st>>>(J, n);
   ptt::k_form_xy<<<dim3(elem_blocks(2LL * c.nb * c.nb), n), kThreads, 0, st>>>(chains, J);
   // (e)-(f): D
@@ -513,7 +529,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   // second pass of an orthonormalisation: Cholesky QR, or the eigenvalue
   // form for the jobs it declines (dims[D_FB] = 0 for the others)
   auto second_pass = [&](const HeevJob* eig, const HeevJob* fallback) {
-    if (h->cholqr) {
+    if (x.cholqr) {
       ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J, ptt::D_GS, ptt::D_FB);
       launch_heev(st, fallback, n, c.kc);
     } else {
@@ -536,15 +552,15 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     const int kb = side ? ptt::D_KZ : ptt::D_KQ;
     const HeevJob* h1 = side ? S.heev_oz : S.heev_oy;
     const HeevJob* h1b = side ? S.heev_ozb : S.heev_oyb;
-    if (h->deflate) defl_dims(0, side);
+    if (x.deflate) defl_dims(0, side);
     launch_gemm(st, J, n, side ? ptt::GK_GRAM_ZA : ptt::GK_GRAM_YA, 1, c.kc, c.kc);
-    launch_heev(st, h1, n, c.kc, h->cholqr ? 0 : 2);
-    if (h->deflate) defl_dims(1, side);
+    launch_heev(st, h1, n, c.kc, x.cholqr ? 0 : 2);
+    if (x.deflate) defl_dims(1, side);
     launch_gemm(st, J, n, side ? ptt::GK_APPLY_ZA : ptt::GK_APPLY_YA, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, kb);
     launch_gemm(st, J, n, side ? ptt::GK_GRAM_ZB : ptt::GK_GRAM_YB, 1, c.kc, c.kc);
     second_pass(h1, h1b);
-    if (!h->deflate) {
+    if (!x.deflate) {
       launch_gemm(st, J, n, side ? ptt::GK_APPLY_ZB : ptt::GK_APPLY_YB, 1, c.dn, c.kc);
       return;
     }
@@ -561,7 +577,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     df(ptt::DF_R2, side, c.dn, c.kc);
     defl_dims(3, side);
     df(ptt::DF_GRAM2B, side, c.kc, c.kc);
-    if (h->cholqr) ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J, ptt::D_G2S, ptt::D_FB2);
+    if (x.cholqr) ptt::k_chol_inv<<<n, ptt::CHOL_THREADS, 0, st>>>(J, ptt::D_G2S, ptt::D_FB2);
     else copy_dim(ptt::D_FB2, ptt::D_G2S);
     launch_heev(st, S.heev_l2b, n, c.kc);
     df(ptt::DF_APPLY2B, side, c.dn, c.kc);
@@ -569,7 +585,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
     ptt::k_defl_copy<<<dim3(elem_blocks((long long)c.dn * c.kc), n), kThreads, 0, st>>>(J, side);
   };
   orth(0);
-  for (int it = 0; it < h->power_iters; ++it) {
+  for (int it = 0; it < x.power_iters; ++it) {
     launch_gemm(st, J, n, ptt::GK_DH_Q, 1, c.dn, c.kc);
     copy_dim(ptt::D_GS, ptt::D_KQ);
     orth(1);
@@ -586,7 +602,7 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   launch_gemm(st, J, n, ptt::GK_GRAM_BM, 1, c.kc, c.kc);
   launch_heev(st, S.heev_rr, n, c.kc);
   launch_gemm(st, J, n, ptt::GK_C, 1, c.kc, c.dn);
-  run_refine(h, S.ref_d, S.heev_ref_d, n, c.kc, c.dn, c.kc);
+  run_refine(x, S.ref_d, S.heev_ref_d, n, c.kc, c.dn, c.kc);
   ptt::k_rule_d<<<(n + 63) / 64, 64, 0, st>>>(J, n);
   launch_gemm(st, J, n, ptt::GK_UD, 1, c.dn, c.chi_cap);
   ptt::k_scale_factors<<<dim3(elem_blocks(2LL * c.dn * c.chi_cap), n), kThreads, 0, st>>>(J);
@@ -599,17 +615,17 @@ void run_sublayer(pt_tebd* h, const Sublayer& S, const ChainDev* chains) {
   ptt::k_logscale<<<1, 64, 0, st>>>(chains, J, n);
 }
 
-void run_half_step(pt_tebd* h, const ChainDev* chains, ChainDev* host_view, double2* /*unused*/) {
-  (void)host_view;
+void run_half_step(pt_tebd* h, const ChainDev* chains) {
+  const Exec x = exec_of(h);
   if (h->n_sites == 1) {
-    ptt::k_apply_site_op<<<elem_blocks((long long)h->cap.chi_cap * h->cap.xi_cap * h->cap.chi_cap), kThreads, 0,
-                           h->stream>>>(chains, 0, h->gates);
+    ptt::k_apply_site_op<<<elem_blocks((long long)x.cap.chi_cap * x.cap.xi_cap * x.cap.chi_cap), kThreads, 0,
+                           x.stream>>>(chains, 0, h->gates);
     return;
   }
   // E(dt/4) O(dt/2) E(dt/4) with 1-based bond parity: E = 0-based odd bonds
-  run_sublayer(h, h->sub_even, chains);
-  run_sublayer(h, h->sub_odd, chains);
-  run_sublayer(h, h->sub_even, chains);
+  run_sublayer(x, h->sub_even, chains);
+  run_sublayer(x, h->sub_odd, chains);
+  run_sublayer(x, h->sub_even, chains);
 }
 
 pt_tebd_status device_status(pt_tebd* h, int which) {
@@ -628,13 +644,13 @@ pt_tebd_status device_status(pt_tebd* h, int which) {
 void step_chain(pt_tebd* h, int which, int k) {
   const ChainDev* chains = h->chains + which;
   // the sublayer jobs index chain 0 of the array they are given
-  run_half_step(h, chains, nullptr, nullptr);
+  run_half_step(h, chains);
   if (h->n_baths > 0) {
     ptt::k_pt_absorb<<<dim3(elem_blocks((long long)h->cap.chi_cap * 4 * h->cap.xi_cap * h->cap.chi_cap), h->n_baths),
                        kThreads, 0, h->stream>>>(chains, h->baths, k);
     ptt::k_pt_commit<<<1, 64 * ((h->n_baths + 63) / 64), 0, h->stream>>>(chains, h->baths, h->n_baths, k);
   }
-  run_half_step(h, chains, nullptr, nullptr);
+  run_half_step(h, chains);
 }
 
 // observe on chain `which` at PT step `k`: fills host num/den/log
@@ -1207,11 +1223,19 @@ void pt_tebd_destroy(pt_tebd_t h) {
 
 pt_tebd_status pt_tebd_step_many(pt_tebd_t* hs, int32_t n, int32_t n_steps) {
   if (!hs || n < 0 || n_steps < 0) return PT_TEBD_EINVAL;
-  for (int i = 0; i < n; ++i) {
-    const pt_tebd_status s = pt_tebd_step(hs[i], n_steps);
-    if (s != PT_TEBD_OK) return s;
-  }
-  return PT_TEBD_OK;
+  if (n == 0 || n_steps == 0) return PT_TEBD_OK;
+  // a transient batch in memory of its own (pt_tebd_batch_* keeps one)
+  size_t bytes = 0;
+  pt_tebd_status s = pt_tebd_batch_workspace_size(hs, n, &bytes);
+  if (s != PT_TEBD_OK) return s;
+  void* ws = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) return PT_TEBD_ENOMEM;
+  pt_tebd_batch_t b = nullptr;
+  s = pt_tebd_batch_create(hs, n, ws, bytes, &b);
+  if (s == PT_TEBD_OK) s = pt_tebd_batch_step(b, n_steps);
+  if (b) pt_tebd_batch_destroy(b);  // synchronises the stream
+  (void)hipFree(ws);
+  return s;
 }
 
 pt_tebd_status pt_tebd_kernel_timing(pt_tebd_t h, int32_t kernel_class) {
@@ -1349,6 +1373,289 @@ void pt_mpo_free(pt_tebd_bath* b) {
 }
 
 }  // extern "C"
+
+// ================================================================== batch
+// Many chains advanced together: every kernel of a sublayer runs once over
+// the bond updates of all chains (the job tables of the chains
+// concatenated), the PT absorption once over all (chain, bath) pairs, and a
+// device step counter per chain keeps the launch sequence identical from
+// step to step, so one step is captured in a HIP graph and replayed.
+struct pt_tebd_batch {
+  std::vector<pt_tebd*> hs;
+  hipStream_t stream = nullptr;
+  Exec x{};
+  Sublayer sub[2];                 // [0] even bonds (1-based), [1] odd bonds
+  ChainDev* chains = nullptr;      // device [n]
+  ptt::BathRef* refs = nullptr;    // device [n_refs]
+  int n_refs = 0;
+  int* kstep = nullptr;            // device [n]
+  std::vector<int> kstep_host;
+  int mixed = 0, gemm_valu = 0;
+  unsigned mixed_mask = ~(1u << 30);
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+};
+
+namespace {
+
+struct BatchPtrs {
+  ChainDev* chains;
+  int* kstep;
+  ptt::BathRef* refs;
+  BondJob* jobs[2];
+  HeevJob *hb[2], *hoy[2], *hoz[2], *hoyb[2], *hozb[2], *hl2[2], *hl2b[2], *hrr[2], *hrb[2], *hrd[2];
+  ptt::RefineJob *rb[2], *rd[2];
+};
+
+size_t batch_layout(int n, const int tot[2], int n_refs, void* base, BatchPtrs* out) {
+  Bump bp(base);
+  BatchPtrs P{};
+  P.chains = bp.take<ChainDev>(n);
+  P.kstep = bp.take<int>(n);
+  P.refs = bp.take<ptt::BathRef>(std::max(n_refs, 1));
+  for (int par = 0; par < 2; ++par) {
+    const int t = std::max(tot[par], 1);
+    P.jobs[par] = bp.take<BondJob>(t);
+    P.hb[par] = bp.take<HeevJob>(2 * t);
+    P.hoy[par] = bp.take<HeevJob>(t);
+    P.hoz[par] = bp.take<HeevJob>(t);
+    P.hoyb[par] = bp.take<HeevJob>(t);
+    P.hozb[par] = bp.take<HeevJob>(t);
+    P.hl2[par] = bp.take<HeevJob>(t);
+    P.hl2b[par] = bp.take<HeevJob>(t);
+    P.hrr[par] = bp.take<HeevJob>(t);
+    P.hrb[par] = bp.take<HeevJob>(2 * t);
+    P.hrd[par] = bp.take<HeevJob>(t);
+    P.rb[par] = bp.take<ptt::RefineJob>(2 * t);
+    P.rd[par] = bp.take<ptt::RefineJob>(t);
+  }
+  if (out) *out = P;
+  return bp.off + 256;
+}
+
+pt_tebd_status batch_check(pt_tebd_t* hs, int n, std::string& err) {
+  if (!hs || n < 1) { err = "empty batch"; return PT_TEBD_EINVAL; }
+  for (int i = 0; i < n; ++i) {
+    const pt_tebd* h = hs[i];
+    if (!h) { err = "null handle in batch"; return PT_TEBD_EINVAL; }
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == h) { err = "a handle appears twice in the batch"; return PT_TEBD_EINVAL; }
+    if (h->n_sites < 2) { err = "batched chains need at least two sites"; return PT_TEBD_EINVAL; }
+    const pt_tebd* f = hs[0];
+    if (h->stream != f->stream) { err = "batched handles must share one stream"; return PT_TEBD_EINVAL; }
+    if (h->precision != f->precision || h->gemm_valu != f->gemm_valu || h->mixed_mask != f->mixed_mask) {
+      err = "batched handles must share the precision";
+      return PT_TEBD_EINVAL;
+    }
+    if (h->power_iters != f->power_iters || h->cholqr != f->cholqr || h->deflate != f->deflate ||
+        h->refine_levels != f->refine_levels || h->refine_tau != f->refine_tau) {
+      err = "batched handles must share the range finder and refinement settings";
+      return PT_TEBD_EINVAL;
+    }
+  }
+  return PT_TEBD_OK;
+}
+
+void batch_counts(pt_tebd_t* hs, int n, int tot[2], int& n_refs) {
+  tot[0] = tot[1] = 0;
+  n_refs = 0;
+  for (int i = 0; i < n; ++i) {
+    tot[0] += (int)hs[i]->sub_even.bonds.size();
+    tot[1] += (int)hs[i]->sub_odd.bonds.size();
+    n_refs += hs[i]->n_baths;
+  }
+}
+
+void batch_enqueue_step(pt_tebd_batch* b) {
+  const Exec& x = b->x;
+  auto half = [&]() {
+    run_sublayer(x, b->sub[0], b->chains);
+    run_sublayer(x, b->sub[1], b->chains);
+    run_sublayer(x, b->sub[0], b->chains);
+  };
+  half();
+  if (b->n_refs > 0) {
+    ptt::k_pt_absorb_batch<<<dim3(elem_blocks((long long)x.cap.chi_cap * 4 * x.cap.xi_cap * x.cap.chi_cap),
+                                  b->n_refs), kThreads, 0, x.stream>>>(b->chains, b->refs, b->kstep);
+    ptt::k_pt_commit_batch<<<(b->n_refs + 63) / 64, 64, 0, x.stream>>>(b->chains, b->refs, b->n_refs, b->kstep);
+  }
+  half();
+  const int n = (int)b->hs.size();
+  ptt::k_advance_steps<<<(n + 63) / 64, 64, 0, x.stream>>>(b->kstep, n);
+}
+
+// the GEMM engine flags of the batch's precision while its steps are enqueued
+struct BatchScope {
+  int pm, pv;
+  unsigned pk;
+  pt_tebd* pt;
+  explicit BatchScope(const pt_tebd_batch* b)
+      : pm(t_gemm_mixed), pv(t_gemm_valu), pk(t_gemm_mixed_mask), pt(t_timing) {
+    t_gemm_mixed = b->mixed;
+    t_gemm_valu = b->gemm_valu;
+    t_gemm_mixed_mask = b->mixed_mask;
+    t_timing = nullptr;
+  }
+  ~BatchScope() {
+    t_gemm_mixed = pm;
+    t_gemm_valu = pv;
+    t_gemm_mixed_mask = pk;
+    t_timing = pt;
+  }
+};
+
+}  // namespace
+
+extern "C" pt_tebd_status pt_tebd_batch_workspace_size(pt_tebd_t* hs, int32_t n, size_t* bytes) {
+  std::string err;
+  if (!bytes) return PT_TEBD_EINVAL;
+  const pt_tebd_status s = batch_check(hs, n, err);
+  if (s != PT_TEBD_OK) return s;
+  int tot[2], n_refs;
+  batch_counts(hs, n, tot, n_refs);
+  *bytes = batch_layout(n, tot, n_refs, nullptr, nullptr);
+  return PT_TEBD_OK;
+}
+
+extern "C" pt_tebd_status pt_tebd_batch_create(pt_tebd_t* hs, int32_t n, void* ws, size_t bytes,
+                                               pt_tebd_batch_t* out) {
+  if (!out) return PT_TEBD_EINVAL;
+  *out = nullptr;
+  std::string err;
+  pt_tebd_status s = batch_check(hs, n, err);
+  if (s != PT_TEBD_OK) { t_create_error = err; return s; }
+  int tot[2], n_refs;
+  batch_counts(hs, n, tot, n_refs);
+  const size_t need = batch_layout(n, tot, n_refs, nullptr, nullptr);
+  if (!ws || bytes < need) { t_create_error = "batch workspace smaller than pt_tebd_batch_workspace_size"; return PT_TEBD_ENOMEM; }
+  BatchPtrs P;
+  batch_layout(n, tot, n_refs, ws, &P);
+  auto b = std::make_unique<pt_tebd_batch>();
+  b->hs.assign(hs, hs + n);
+  const pt_tebd* f = hs[0];
+  b->stream = f->stream;
+  b->mixed = f->precision == PT_TEBD_FP32_MIXED ? 1 : 0;
+  b->gemm_valu = f->gemm_valu;
+  b->mixed_mask = f->mixed_mask;
+  b->use_graph = env_int("PT_TEBD_GRAPH", 1) != 0 && b->stream != nullptr;
+  Caps c = f->cap;
+  for (int i = 1; i < n; ++i) {
+    const Caps& d = hs[i]->cap;
+    c.chi_cap = std::max(c.chi_cap, d.chi_cap); c.xi_cap = std::max(c.xi_cap, d.xi_cap);
+    c.nb = std::max(c.nb, d.nb); c.dn = std::max(c.dn, d.dn); c.kc = std::max(c.kc, d.kc);
+    c.ks = std::max(c.ks, d.ks); c.nh = std::max(c.nh, d.nh); c.gam_cap = std::max(c.gam_cap, d.gam_cap);
+  }
+  b->x = Exec{b->stream, c, f->power_iters, f->cholqr, f->deflate, f->refine_levels, f->refine_tau};
+  hipStream_t st = b->stream;
+  bool ok = true;
+  auto cp = [&](void* dst, const void* src, size_t len, hipMemcpyKind kind) {
+    ok = ok && hipMemcpyAsync(dst, src, len, kind, st) == hipSuccess;
+  };
+  std::vector<ChainDev> ch(n);
+  std::vector<ptt::BathRef> refs;
+  for (int i = 0; i < n; ++i) {
+    ch[i] = hs[i]->chain_host[0];
+    for (int j = 0; j < hs[i]->n_baths; ++j) refs.push_back(ptt::BathRef{i, 0, hs[i]->baths + j});
+  }
+  cp(P.chains, ch.data(), n * sizeof(ChainDev), hipMemcpyHostToDevice);
+  if (n_refs) cp(P.refs, refs.data(), n_refs * sizeof(ptt::BathRef), hipMemcpyHostToDevice);
+  b->n_refs = n_refs;
+  for (int par = 0; par < 2; ++par) {
+    Sublayer& S = b->sub[par];
+    S.jobs = P.jobs[par]; S.heev_b = P.hb[par]; S.heev_oy = P.hoy[par]; S.heev_oz = P.hoz[par];
+    S.heev_oyb = P.hoyb[par]; S.heev_ozb = P.hozb[par]; S.heev_l2 = P.hl2[par]; S.heev_l2b = P.hl2b[par];
+    S.heev_rr = P.hrr[par]; S.ref_b = P.rb[par]; S.ref_d = P.rd[par]; S.heev_ref_b = P.hrb[par];
+    S.heev_ref_d = P.hrd[par];
+    int off = 0;
+    for (int i = 0; i < n; ++i) {
+      const Sublayer& H = par == 0 ? hs[i]->sub_even : hs[i]->sub_odd;
+      const int m = (int)H.bonds.size();
+      if (m == 0) continue;
+      for (int j = 0; j < m; ++j) {
+        BondJob J = H.host_jobs[j];
+        J.chain = i;
+        S.host_jobs.push_back(J);
+        S.bonds.push_back(H.bonds[j]);
+      }
+      auto d2d = [&](void* dst_base, const void* src, size_t per, int count) {
+        cp(static_cast<char*>(dst_base) + per * (size_t)off * (count / m), src, per * count, hipMemcpyDeviceToDevice);
+      };
+      d2d(S.heev_b, H.heev_b, sizeof(HeevJob), 2 * m);
+      d2d(S.heev_oy, H.heev_oy, sizeof(HeevJob), m);
+      d2d(S.heev_oz, H.heev_oz, sizeof(HeevJob), m);
+      d2d(S.heev_oyb, H.heev_oyb, sizeof(HeevJob), m);
+      d2d(S.heev_ozb, H.heev_ozb, sizeof(HeevJob), m);
+      d2d(S.heev_l2, H.heev_l2, sizeof(HeevJob), m);
+      d2d(S.heev_l2b, H.heev_l2b, sizeof(HeevJob), m);
+      d2d(S.heev_rr, H.heev_rr, sizeof(HeevJob), m);
+      d2d(S.heev_ref_b, H.heev_ref_b, sizeof(HeevJob), 2 * m);
+      d2d(S.heev_ref_d, H.heev_ref_d, sizeof(HeevJob), m);
+      d2d(S.ref_b, H.ref_b, sizeof(ptt::RefineJob), 2 * m);
+      d2d(S.ref_d, H.ref_d, sizeof(ptt::RefineJob), m);
+      off += m;
+    }
+    if (!S.host_jobs.empty()) cp(S.jobs, S.host_jobs.data(), S.host_jobs.size() * sizeof(BondJob), hipMemcpyHostToDevice);
+  }
+  b->chains = P.chains;
+  b->refs = P.refs;
+  b->kstep = P.kstep;
+  b->kstep_host.assign(n, 0);
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) { t_create_error = "batch set-up copies failed"; return PT_TEBD_EDEVICE; }
+  *out = b.release();
+  return PT_TEBD_OK;
+}
+
+extern "C" pt_tebd_status pt_tebd_batch_step(pt_tebd_batch_t b, int32_t n_steps) {
+  if (!b || n_steps < 0) return PT_TEBD_EINVAL;
+  for (pt_tebd* h : b->hs)
+    if (h->n_baths > 0 && h->step + n_steps > h->pt_steps) {
+      b->err = "stepping past the end of a PT-MPO";
+      return PT_TEBD_ERANGE;
+    }
+  if (n_steps == 0) return PT_TEBD_OK;
+  BatchScope scope(b);
+  hipStream_t st = b->stream;
+  for (size_t i = 0; i < b->hs.size(); ++i) b->kstep_host[i] = b->hs[i]->step;
+  if (hipMemcpyAsync(b->kstep, b->kstep_host.data(), b->hs.size() * sizeof(int), hipMemcpyHostToDevice, st) !=
+      hipSuccess) { b->err = "step counter upload"; return PT_TEBD_EDEVICE; }
+  if (b->use_graph) {
+    if (!b->gexec) {
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        b->err = "graph capture could not start";
+        return PT_TEBD_EDEVICE;
+      }
+      batch_enqueue_step(b);
+      if (hipStreamEndCapture(st, &b->graph) != hipSuccess ||
+          hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        b->err = "graph capture or instantiation failed";
+        return PT_TEBD_EDEVICE;
+      }
+    }
+    for (int k = 0; k < n_steps; ++k)
+      if (hipGraphLaunch(b->gexec, st) != hipSuccess) { b->err = "graph launch"; return PT_TEBD_EDEVICE; }
+  } else {
+    for (int k = 0; k < n_steps; ++k) batch_enqueue_step(b);
+  }
+  if (hipGetLastError() != hipSuccess) { b->err = "kernel launch"; return PT_TEBD_EDEVICE; }
+  for (pt_tebd* h : b->hs) h->step += n_steps;
+  return PT_TEBD_OK;
+}
+
+extern "C" const char* pt_tebd_batch_last_error(pt_tebd_batch_t b) {
+  if (b) return b->err.c_str();
+  return t_create_error.empty() ? "null batch" : t_create_error.c_str();
+}
+
+extern "C" void pt_tebd_batch_destroy(pt_tebd_batch_t b) {
+  if (!b) return;
+  hipStreamSynchronize(b->stream);
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
+}
 
 // ------------------------------------------------------------ test hooks
 #include "pt_tebd_testing.h"
