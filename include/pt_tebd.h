@@ -219,6 +219,25 @@ pt_tebd_status pt_mpo_build_ohmic(double alpha, double wc, int32_t cutoff_kind, 
                                   pt_tebd_bath* out);
 void pt_mpo_free(pt_tebd_bath* bath);
 
+/* The same PT-MPO construction (Appendix B.1) for n_builds baths at once on
+ * the GPU: every bath is one work item of the batched window sweeps (right
+ * to left LQ factorisations, left to right truncated SVDs through Gram
+ * matrices and the double-precision eigensolver).  params[b] gives alpha,
+ * wc, temperature, cutoff_kind and the coupling operator of bath b; dt,
+ * n_steps, mem_steps, eps and xi_max (<= 256) are shared.  out[b] is filled
+ * as by pt_mpo_build_ohmic (library-owned host arrays, free each with
+ * pt_mpo_free).  Device memory (about (mem_steps + 6) (4 xi_max)^2 * 64 B
+ * plus n_steps xi_max^2 * 64 B per bath) is allocated and freed by the call;
+ * work runs on hip_stream, and the call synchronises it. */
+typedef struct {
+  double alpha, wc, temperature;
+  int32_t cutoff_kind;
+  const double* coupling_op;   /* d x d Hermitian, complex */
+} pt_bath_params;
+pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_bath_params* params, double dt,
+                                        int32_t n_steps, int32_t mem_steps, double eps, int32_t xi_max,
+                                        int32_t d, void* hip_stream, pt_tebd_bath* out);
+
 /* eta_Delta (Delta = 0..mem_steps) of the same discretisation, complex
  * [mem_steps + 1]; exposed for testing. */
 pt_tebd_status pt_bath_eta(double alpha, double wc, int32_t cutoff_kind, double temperature,

@@ -24,6 +24,14 @@ extern "C" {
 pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
                             double* w, double* v, int32_t* nvec);
 
+/* pt_test_heev that also returns the real tridiagonal matrix T = Q^H a Q of
+ * the first stage (tri[0..n): diagonal, tri[n..2n): off-diagonal, entry i
+ * coupling rows i and i + 1) and the eigenvectors of T before the
+ * back-transformation (z, row-major n x n; column k pairs with w[k] for the
+ * selected columns k < *nvec). */
+pt_tebd_status pt_test_heev_tridiagonal(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
+                                        double* w, double* v, int32_t* nvec, double* tri, double* z);
+
 #ifdef __cplusplus
 }
 #endif

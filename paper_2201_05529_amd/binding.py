@@ -31,6 +31,11 @@ class Bath(ctypes.Structure):
                 ("caps", ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))]
 
 
+class BathParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("wc", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("cutoff_kind", ctypes.c_int32), ("coupling_op", ctypes.POINTER(ctypes.c_double))]
+
+
 class Config(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("d", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("h_site", ctypes.POINTER(ctypes.c_double)), ("h_bond", ctypes.POINTER(ctypes.c_double)),
@@ -79,6 +84,8 @@ def lib():
         L.pt_mpo_build_ohmic.argtypes = [dbl, dbl, i32, dbl, dbl, i32, i32, dbl, i32, dp, i32, ctypes.POINTER(Bath)]
         L.pt_mpo_free.argtypes = [ctypes.POINTER(Bath)]
         L.pt_heev_noalloc.argtypes = [i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
+        L.pt_mpo_build_ohmic_batch.argtypes = [i32, ctypes.POINTER(BathParams), dbl, i32, i32, dbl, i32, i32, vp,
+                                               ctypes.POINTER(Bath)]
         L.pt_tebd_batch_workspace_size.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_size_t)]
         L.pt_tebd_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.pt_tebd_batch_step.argtypes = [vp, i32]
@@ -132,6 +139,44 @@ def build_ptmpo(alpha, wc, temperature, dt, n_steps, mem_steps, eps, xi_max, cou
         return {"tensors": tensors, "bond_dims": dims, "diagonal": bool(b.diagonal)}
     finally:
         lib().pt_mpo_free(ctypes.byref(b))
+
+
+def _bath_to_dict(b, n_steps):
+    dims = [b.bond_dims[k] for k in range(n_steps + 1)]
+    per = 4 if b.diagonal else 16
+    tensors = []
+    for k in range(n_steps):
+        n = dims[k] * dims[k + 1] * per
+        flat = np.ctypeslib.as_array(b.tensors[k], shape=(2 * n,)).copy().view(np.complex128)
+        shape = (dims[k], dims[k + 1], 4) if b.diagonal else (dims[k], dims[k + 1], 4, 4)
+        tensors.append(flat.reshape(shape))
+    return {"tensors": tensors, "bond_dims": dims, "diagonal": bool(b.diagonal)}
+
+
+def build_ptmpo_batch(baths, dt, n_steps, mem_steps, eps, xi_max, stream=None):
+    """PT-MPOs of many baths at once on the GPU (pt_mpo_build_ohmic_batch).
+    `baths`: list of dict(alpha, wc, temperature, coupling_op, cutoff='exp')."""
+    import torch
+    n = len(baths)
+    ops = [_cplx(b["coupling_op"]) for b in baths]
+    params = (BathParams * n)()
+    for i, b in enumerate(baths):
+        params[i].alpha, params[i].wc, params[i].temperature = b["alpha"], b["wc"], b["temperature"]
+        params[i].cutoff_kind = 0 if b.get("cutoff", "exp") == "exp" else 1
+        params[i].coupling_op = _dptr(ops[i])
+    outs = (Bath * n)()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().pt_mpo_build_ohmic_batch(n, params, float(dt), int(n_steps), int(mem_steps), float(eps), int(xi_max),
+                                        2, ctypes.c_void_p(s.cuda_stream), outs)
+    if st != 0:
+        raise PtTebdError(st, "pt_mpo_build_ohmic_batch")
+    res = []
+    for i in range(n):
+        try:
+            res.append(_bath_to_dict(outs[i], n_steps))
+        finally:
+            lib().pt_mpo_free(ctypes.byref(outs[i]))
+    return res
 
 
 class Chain:

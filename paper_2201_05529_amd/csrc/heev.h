@@ -4,21 +4,28 @@
 //
 //  stage 1  Householder reduction A = Q T Q^H, T real symmetric tridiagonal
 //           (reflector H_j = I - tau_j v_j v_j^H, H_j^H x = beta e_1)
-//  stage 2  T + delta I = L D L^T with D > 0 (delta a few ulps of |T|, more
+//  stage 2  off-diagonal entries of T at the rounding level of |T| are set
+//           to zero, which splits T into unreduced blocks; then
+//           T + delta I = L D L^T with D > 0 (delta a few ulps of |T|, more
 //           if needed, so the factorisation exists)
-//  stage 3  every eigenvalue of L D L^T: a shared grid of qd negative counts
-//           brackets all of them, then multisection to high relative
-//           accuracy (those at the rounding level keep the bracket); then
-//           the selection rule (truncated-SVD
-//           rule of Appendix A.2, or a numerical-rank rule) fixes how many
-//           leading eigenpairs are needed
-//  stage 4  their eigenvectors of T from twisted factorisations (one O(n)
-//           solve per vector); clusters of numerically equal eigenvalues
+//  stage 3  every eigenvalue of each block of L D L^T: a shared grid of qd
+//           negative counts brackets all of them, then multisection to high
+//           relative accuracy; the values of all blocks are merged into one
+//           descending list that remembers each value's block; then the
+//           selection rule (truncated-SVD rule of Appendix A.2, or a
+//           numerical-rank rule) fixes how many leading eigenpairs are
+//           needed
+//  stage 4  their eigenvectors of T from twisted factorisations of their
+//           own block (one O(block) solve per vector, zero outside the
+//           block); within a block, clusters of numerically equal eigenvalues
 //           get random starts, inverse iteration and Gram-Schmidt against
 //           the cluster and its near neighbours; eigenvalues within the
 //           rounding level of zero (the numerical null space of a singular
-//           Gram matrix) form one such cluster, orthogonalised against all
-//           other vectors
+//           Gram matrix) form one cluster over all blocks, orthogonalised
+//           against all other vectors.  Equal eigenvalues of different
+//           blocks (exact degeneracies, common in Gram matrices of
+//           symmetric states) need no special care: their vectors have
+//           disjoint supports
 //  stage 5  (separate kernel) back-transformation V = Q Z with the stored
 //           reflectors
 //  stage 6  (separate kernels) two passes of block classical Gram-Schmidt
@@ -121,7 +128,9 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   __shared__ double red[NT / 64];
   __shared__ double2 s_tau;
   __shared__ double s_beta, s_delta, s_tnorm;
-  __shared__ int s_nvec, s_ok;
+  __shared__ int s_nvec, s_ok, s_nb, s_nref;
+  __shared__ int s_bs[1025];  // block b of T covers rows [s_bs[b], s_bs[b + 1])
+  __shared__ int s_kb[1024];  // block of the eigenvalue mu[j] (ascending order)
   double2* A = J.a;
   const int lda = J.lda;
   const int nc = J.n_cap;
@@ -283,6 +292,17 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
       tn = fmax(tn, r);
     }
     s_tnorm = tn;
+    // split T where a coupling is at the rounding level of |T| (a
+    // perturbation of T no larger than the rounding errors of stage 1)
+    int nb = 0;
+    s_bs[0] = 0;
+    for (int i = 0; i + 1 < n; ++i)
+      if (fabs(ee[i]) <= 2.2e-16 * tn) {
+        ee[i] = 0.0;
+        s_bs[++nb] = i + 1;
+      }
+    s_bs[++nb] = n;
+    s_nb = nb;
     int ok = 0;
     double delta = fmax(8.0 * n * 2.2e-16 * tn, 1e-300);
     if (tn > 0.0) {
@@ -318,57 +338,65 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     }
     if (tnorm > 0.0 && tid == 0) atomicOr(J.status, 1);
   } else {
-    // -------- stage 3: eigenvalues of L D L^T.  (a) one shared pass: every
-    // thread counts the eigenvalues below one point of a geometric grid over
+    // -------- stage 3: eigenvalues of each block of L D L^T (the qd
+    // recurrence restarts at a split, so a count over the whole matrix is
+    // the sum of the blocks' counts).  (a) one shared pass: every thread
+    // counts the eigenvalues below one point of a geometric grid over
     // [1e-40 top, top], which brackets every eigenvalue to a factor 1.1;
     // (b) each is refined by multisection with a group of te threads
     // (te + 1 geometric subintervals per round) down to a few ulps
-    // (relative accuracy).
+    // (relative accuracy).  Slot g holds eigenvalue g - s_bs[b] (ascending)
+    // of the block b that contains row g.
     const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
+    const int nb = s_nb;
     double* xg = buf + 6144;
     int* cg = reinterpret_cast<int*>(buf + 7168);
+    double* val = (nb > 1) ? buf + 5120 : mu;  // slot values (merged into mu below)
     const double top = 1.01 * (tnorm + delta) + 1e-300;
     const double bot = fmax(1e-40 * top, 1e-300);
     {
       const double x = bot * exp((double)tid / (NT - 1) * log(top / bot));
       xg[tid] = x;
-      cg[tid] = ldl_negcount(d, lld, n, x, pivmin);
+      cg[tid] = (nb == 1) ? ldl_negcount(d, lld, n, x, pivmin) : 0;
     }
     __syncthreads();
-    const int knoise = 0;  // every eigenvalue is refined (relative accuracy keeps twisted vectors orthogonal)
-    auto bracket = [&](int k, double& lo, double& hi) {
-      int a = 0, b = NT;  // first grid point with more than k eigenvalues below
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (cg[mid] > k) b = mid;
-        else a = mid + 1;
-      }
-      hi = (a < NT) ? xg[a] : top;
-      lo = (a > 0) ? xg[a - 1] : 1e-300 * top;
-    };
-    for (int k = tid; k < knoise; k += NT) {
-      double lo, hi;
-      bracket(k, lo, hi);
-      const double m_k = fmin(0.5 * (lo + hi), 2.0 * delta);
-      mu[k] = m_k;
-      J.w[n - 1 - k] = m_k - delta;
-    }
-    const int nr = n - knoise;
     int te = 1;
-    while (te < 64 && te * 2 * max(nr, 1) <= NT) te *= 2;
+    while (te < 64 && te * 2 * max(n, 1) <= NT) te *= 2;
     const int q = tid % te;
     const int base = (tid & 63) & ~(te - 1);
-    for (int k0 = knoise; k0 < n; k0 += NT / te) {
-      const int k = k0 + tid / te;
+    for (int g0 = 0; g0 < n; g0 += NT / te) {
+      const int g = g0 + tid / te;
       double lo = 0.0, hi = 0.0;
-      if (k < n) {
-        bracket(k, lo, hi);
+      if (g < n) {
+        int b = 0;
+        if (nb > 1) {  // last block starting at or before row g
+          int a = 0, c = nb;
+          while (c - a > 1) {
+            const int m = (a + c) >> 1;
+            if (s_bs[m] <= g) a = m;
+            else c = m;
+          }
+          b = a;
+        }
+        const int r0 = s_bs[b], len = s_bs[b + 1] - r0, k = g - r0;
+        const double* db = d + r0;
+        const double* lb = lld + r0;
+        // first grid point with more than k eigenvalues of the block below
+        int a = 0, c = NT;
+        while (a < c) {
+          const int m = (a + c) >> 1;
+          const int cnt = (nb == 1) ? cg[m] : ldl_negcount(db, lb, len, xg[m], pivmin);
+          if (cnt > k) c = m;
+          else a = m + 1;
+        }
+        hi = (a < NT) ? xg[a] : top;
+        lo = (a > 0) ? xg[a - 1] : 1e-300 * top;
         const double f = (q + 1) / (double)(te + 1);
         for (int it = 0; it < 120; ++it) {
           if (hi - lo <= 4.4e-16 * hi) break;
           const bool geo = lo > 0.0 && hi > 4.0 * lo;
           const double x = geo ? lo * exp(f * log(hi / lo)) : lo + f * (hi - lo);
-          const int cnt = ldl_negcount(d, lld, n, x, pivmin);
+          const int cnt = ldl_negcount(db, lb, len, x, pivmin);
           double nlo = lo, nhi = hi;
           for (int r = 0; r < te; ++r) {
             const double xr = __shfl(x, base + r, 64);
@@ -379,13 +407,35 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
           lo = nlo;
           hi = nhi;
         }
-      }
-      if (k < n && q == 0) {
-        const double m_k = 0.5 * (lo + hi);
-        mu[k] = m_k;
-        J.w[n - 1 - k] = m_k - delta;
+        if (q == 0) {
+          val[g] = 0.5 * (lo + hi);
+          if (nb == 1) s_kb[g] = 0;
+        }
       }
     }
+    __syncthreads();
+    if (nb > 1) {
+      // merge: ascending position of slot g = number of smaller values
+      // (equal values ordered by slot)
+      for (int g = tid; g < n; g += NT) {
+        const double v = val[g];
+        int pos = 0;
+        for (int h = 0; h < n; ++h) {
+          const double u = val[h];
+          pos += (u < v) || (u == v && h < g);
+        }
+        int a = 0, c = nb;
+        while (c - a > 1) {
+          const int m = (a + c) >> 1;
+          if (s_bs[m] <= g) a = m;
+          else c = m;
+        }
+        mu[pos] = v;
+        s_kb[pos] = a;
+      }
+      __syncthreads();
+    }
+    for (int j = tid; j < n; j += NT) J.w[n - 1 - j] = mu[j] - delta;
   }
   __syncthreads();
 
@@ -455,23 +505,31 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   }
   const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
   const int nres = nvec;
+  // rows [r0, r1) of the block that holds the eigenvalue of descending index k
+  auto block_of = [&](int k, int& r0, int& r1) {
+    const int b = s_kb[n - 1 - k];
+    r0 = s_bs[b];
+    r1 = s_bs[b + 1];
+  };
   for (int k = tid; k < nres; k += NT) {
     const double m_k = mu[n - 1 - k];
+    int r0, r1;
+    block_of(k, r0, r1);
     // top-down (stationary)
     double s = -m_k;
-    for (int i = 0; i + 1 < n; ++i) {
+    for (int i = r0; i + 1 < r1; ++i) {
       W(1, i, k) = s;
       double dp = d[i] + s;
       if (fabs(dp) < pivmin) dp = dp < 0.0 ? -pivmin : pivmin;
       W(0, i, k) = ld[i] / dp;
       s = lld[i] * (s / dp) - m_k;
     }
-    W(1, n - 1, k) = s;
+    W(1, r1 - 1, k) = s;
     // bottom-up (progressive) with the twist index
-    double p = d[n - 1] - m_k;
-    double gmin = fabs(W(1, n - 1, k) + p + m_k);
-    int r = n - 1;
-    for (int i = n - 2; i >= 0; --i) {
+    double p = d[r1 - 1] - m_k;
+    double gmin = fabs(W(1, r1 - 1, k) + p + m_k);
+    int r = r1 - 1;
+    for (int i = r1 - 2; i >= r0; --i) {
       double dm = lld[i] + p;
       if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
       const double t = d[i] / dm;
@@ -483,36 +541,45 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     // solve
     double z = 1.0, nrm = 1.0;
     Z(r, k) = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
+    for (int i = r - 1; i >= r0; --i) {
       z = -W(0, i, k) * z;
       Z(i, k) = z;
       nrm += z * z;
     }
     z = 1.0;
-    for (int i = r; i + 1 < n; ++i) {
+    for (int i = r; i + 1 < r1; ++i) {
       z = -W(2, i, k) * z;
       Z(i + 1, k) = z;
       nrm += z * z;
     }
     const double inv = (nrm > 0.0 && nrm < 1e300) ? 1.0 / sqrt(nrm) : 0.0;
-    if (inv > 0.0) {
-      for (int i = 0; i < n; ++i) Z(i, k) *= inv;
-    } else {  // overflow: fall back to the unit vector at the twist index
-      for (int i = 0; i < n; ++i) Z(i, k) = (i == r) ? 1.0 : 0.0;
+    for (int i = 0; i < n; ++i) {
+      const bool in = i >= r0 && i < r1;
+      // overflow: fall back to the unit vector at the twist index
+      Z(i, k) = !in ? 0.0 : (inv > 0.0 ? Z(i, k) * inv : (i == r ? 1.0 : 0.0));
     }
   }
   __syncthreads();
 
   // -------- stage 4b: clusters of numerically equal eigenvalues (relative
-  // gap below 1e-9).  Twisted vectors of equal mu coincide, so every member
-  // after the first restarts from a seeded random vector, takes three
-  // inverse-iteration solves (pivoted elimination of T - lambda I), and is
-  // orthogonalised against the earlier members and near neighbours.
-  // Eigenvalues of T within delta of zero are rounding noise of a
+  // gap below 1e-9) inside one block.  Twisted vectors of equal mu
+  // coincide, so every member after the first restarts from a seeded random
+  // vector on the block's rows and takes three inverse-iteration solves
+  // (pivoted elimination of the block of T - lambda I); after each solve it
+  // is orthogonalised against the vectors of its block near it that are
+  // already final (the twisted ones and the earlier members of its cluster),
+  // since the solve alone amplifies whichever member of the cluster has the
+  // smallest pivot and would lose the others to rounding.  Members of
+  // different clusters run in parallel, the r-th members of all clusters in
+  // round r.  Clusters of more than four values (near-multiples of the
+  // identity on a block) skip the per-solve projection and take all their
+  // members in the first round: their solves amplify the members evenly.  A
+  // final Gram-Schmidt over the members in order follows.  Eigenvalues of T within delta of zero are rounding noise of a
   // (numerically) singular matrix, not values known to any relative
-  // accuracy: they form one cluster whatever their relative gaps, every
-  // member of it (the first one too) is computed by inverse iteration, and
-  // each is orthogonalised against all other vectors.
+  // accuracy: they form one cluster over all blocks whatever their relative
+  // gaps, every member of it (the first one too) is a seeded random vector
+  // of the whole space, and each is orthogonalised against all other
+  // vectors.
   {
     const double rgap = 1e-9;
     // |lambda| below the initial shift (8 n eps |T|) is rounding noise;
@@ -520,96 +587,194 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     const double noise = 8.0 * n * 2.2e-16 * tnorm;
     const bool use_noise = J.noise_cluster != 0;
     auto is_noise = [&](int a) { return use_noise && fabs(mu[n - 1 - a] - delta) <= noise; };
-    auto same = [&](int a, int b) {  // a, b descending-order indices
+    auto close = [&](int a, int b) {  // a, b descending-order indices
       const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
-      return (is_noise(a) && is_noise(b)) || fabs(ma - mb) <= rgap * fmax(fabs(ma), fabs(mb));
+      return fabs(ma - mb) <= rgap * fmax(fabs(ma), fabs(mb));
+    };
+    // k repeats the eigenvalue of an earlier index of its own block (the
+    // indices between two close values hold close values too)
+    // number of earlier indices of k's block with a close eigenvalue (0: not
+    // a member)
+    auto member_rank = [&](int k) {
+      if (is_noise(k)) return 0;
+      const int bk = s_kb[n - 1 - k];
+      int r = 0;
+      for (int i = k - 1; i >= 0 && close(i, k); --i) r += s_kb[n - 1 - i] == bk;
+      return r;
+    };
+    auto is_member = [&](int k) { return member_rank(k) > 0; };
+    constexpr int SMALL_CLUSTER = 4;
+    // more than SMALL_CLUSTER same-block values close to k's
+    auto big_cluster = [&](int k) {
+      if (is_noise(k)) return false;
+      const int bk = s_kb[n - 1 - k];
+      int c = 1;
+      for (int i = k - 1; i >= 0 && close(i, k) && c <= SMALL_CLUSTER; --i) c += s_kb[n - 1 - i] == bk;
+      for (int i = k + 1; i < nres && close(i, k) && c <= SMALL_CLUSTER; ++i) c += s_kb[n - 1 - i] == bk;
+      return c > SMALL_CLUSTER;
+    };
+    auto near = [&](int a, int b) {
+      const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
+      return fabs(ma - mb) <= 1e-3 * fmax(fabs(ma), fabs(mb));
     };
     // pivots of the (nearly) singular shifted matrix are floored at
     // eps |T|, as in inverse iteration: the solve then amplifies the
     // eigenspace without overflowing
     const double pfloor = fmax(2.2e-16 * tnorm, pivmin);
-    // members: k with k > 0 and same(k - 1, k)
-    for (int k = tid; k < nres; k += NT) {
-      if (!is_noise(k) && (k == 0 || !same(k - 1, k))) continue;
+    for (int k = tid; k < nres; k += NT)
       if (is_noise(k)) {
         // any vector of the null space will do: a seeded random start,
         // projected onto the complement of the other vectors below
         for (int i = 0; i < n; ++i) Z(i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
-        continue;
       }
-      // inverse iteration with T - lambda I factored by Gaussian elimination
-      // with partial pivoting (bounded growth; pivots floored at eps |T|)
-      const double lam = mu[n - 1 - k] - delta;
-      for (int i = 0; i < n; ++i) {
-        W(0, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // sub-diagonal, then multipliers
-        W(1, i, k) = dd[i] - lam;                // diagonal of U
-        W(2, i, k) = (i + 1 < n) ? ee[i] : 0.0;  // first super-diagonal of U
-        W(3, i, k) = 0.0;                        // second super-diagonal of U
-        W(4, i, k) = 0.0;                        // row swap at step i
-      }
-      for (int i = 0; i + 1 < n; ++i) {
-        const double di = W(1, i, k), li = W(0, i, k);
-        if (fabs(di) >= fabs(li)) {
-          W(0, i, k) = (di != 0.0) ? li / di : 0.0;
-          W(1, i + 1, k) -= W(0, i, k) * W(2, i, k);
-        } else {
-          const double f = di / li;
-          W(1, i, k) = li;
-          W(0, i, k) = f;
-          const double tmp = W(2, i, k);
-          W(2, i, k) = W(1, i + 1, k);
-          W(1, i + 1, k) = tmp - f * W(1, i + 1, k);
-          if (i + 2 < n) {
-            W(3, i, k) = W(2, i + 1, k);
-            W(2, i + 1, k) = -f * W(2, i + 1, k);
+    for (int round = 1; round < SMALL_CLUSTER; ++round) {
+      for (int k = tid; k < nres; k += NT) {
+        const int rk = member_rank(k);
+        const bool big = rk > 0 && big_cluster(k);
+        if (big ? round != 1 : rk != round) continue;
+        // inverse iteration on the rows [r0, r1) of the block, T - lambda I
+        // factored by Gaussian elimination with partial pivoting (bounded
+        // growth; pivots floored at eps |T|)
+        int r0, r1;
+        block_of(k, r0, r1);
+        const int bk = s_kb[n - 1 - k];
+        int na = k, nb = k + 1;
+        while (na > 0 && near(na - 1, k)) --na;
+        while (nb < nres && near(nb, k)) ++nb;
+        // final vectors of the block near k: twisted ones and members of
+        // small clusters from earlier rounds
+        auto final_ref = [&](int i) {
+          if (i == k || s_kb[n - 1 - i] != bk || is_noise(i)) return false;
+          const int ri = member_rank(i);
+          return ri == 0 || (ri < round && !big_cluster(i));
+        };
+        const double lam = mu[n - 1 - k] - delta;
+        for (int i = r0; i < r1; ++i) {
+          W(0, i, k) = (i + 1 < r1) ? ee[i] : 0.0;  // sub-diagonal, then multipliers
+          W(1, i, k) = dd[i] - lam;                 // diagonal of U
+          W(2, i, k) = (i + 1 < r1) ? ee[i] : 0.0;  // first super-diagonal of U
+          W(3, i, k) = 0.0;                         // second super-diagonal of U
+          W(4, i, k) = 0.0;                         // row swap at step i
+        }
+        for (int i = r0; i + 1 < r1; ++i) {
+          const double di = W(1, i, k), li = W(0, i, k);
+          if (fabs(di) >= fabs(li)) {
+            W(0, i, k) = (di != 0.0) ? li / di : 0.0;
+            W(1, i + 1, k) -= W(0, i, k) * W(2, i, k);
+          } else {
+            const double f = di / li;
+            W(1, i, k) = li;
+            W(0, i, k) = f;
+            const double tmp = W(2, i, k);
+            W(2, i, k) = W(1, i + 1, k);
+            W(1, i + 1, k) = tmp - f * W(1, i + 1, k);
+            if (i + 2 < r1) {
+              W(3, i, k) = W(2, i + 1, k);
+              W(2, i + 1, k) = -f * W(2, i + 1, k);
+            }
+            W(4, i, k) = 1.0;
           }
-          W(4, i, k) = 1.0;
         }
-      }
-      for (int i = 0; i < n; ++i)
-        if (fabs(W(1, i, k)) < pfloor) W(1, i, k) = W(1, i, k) >= 0.0 ? pfloor : -pfloor;
-      for (int i = 0; i < n; ++i) W(5, i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
-      for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i + 1 < n; ++i) {  // P, L
-          if (W(4, i, k) != 0.0) {
-            const double t = W(5, i, k);
-            W(5, i, k) = W(5, i + 1, k);
-            W(5, i + 1, k) = t;
+        for (int i = r0; i < r1; ++i)
+          if (fabs(W(1, i, k)) < pfloor) W(1, i, k) = W(1, i, k) >= 0.0 ? pfloor : -pfloor;
+        for (int i = r0; i < r1; ++i) W(5, i, k) = u01(splitmix64(0xA24BAED4963EE407ull * (k + 1) + i)) - 0.5;
+        for (int it = 0; it < 3; ++it) {
+          for (int i = r0; i + 1 < r1; ++i) {  // P, L
+            if (W(4, i, k) != 0.0) {
+              const double t = W(5, i, k);
+              W(5, i, k) = W(5, i + 1, k);
+              W(5, i + 1, k) = t;
+            }
+            W(5, i + 1, k) -= W(0, i, k) * W(5, i, k);
           }
-          W(5, i + 1, k) -= W(0, i, k) * W(5, i, k);
+          for (int i = r1 - 1; i >= r0; --i) {  // U
+            double acc = W(5, i, k);
+            if (i + 1 < r1) acc -= W(2, i, k) * W(6, i + 1, k);
+            if (i + 2 < r1) acc -= W(3, i, k) * W(6, i + 2, k);
+            W(6, i, k) = acc / W(1, i, k);
+          }
+          double nr = 0.0;
+          for (int i = r0; i < r1; ++i) nr += W(6, i, k) * W(6, i, k);
+          double inv = (nr > 0.0 && nr < 1e300) ? 1.0 / sqrt(nr) : 0.0;
+          for (int i = r0; i < r1; ++i) W(5, i, k) = W(6, i, k) * inv;
+          // modified Gram-Schmidt against the final vectors near k
+          for (int p = na; p < nb && !big; ++p) {
+            if (!final_ref(p)) continue;
+            double dot = 0.0;
+            for (int i = r0; i < r1; ++i) dot += Z(i, p) * W(5, i, k);
+            for (int i = r0; i < r1; ++i) W(5, i, k) -= dot * Z(i, p);
+          }
+          nr = 0.0;
+          for (int i = r0; i < r1; ++i) nr += W(5, i, k) * W(5, i, k);
+          inv = (nr > 0.0 && nr < 1e300) ? 1.0 / sqrt(nr) : 0.0;
+          for (int i = r0; i < r1; ++i) W(5, i, k) *= inv;
         }
-        for (int i = n - 1; i >= 0; --i) {  // U
-          double acc = W(5, i, k);
-          if (i + 1 < n) acc -= W(2, i, k) * W(6, i + 1, k);
-          if (i + 2 < n) acc -= W(3, i, k) * W(6, i + 2, k);
-          W(6, i, k) = acc / W(1, i, k);
-        }
-        double nr = 0.0;
-        for (int i = 0; i < n; ++i) nr += W(6, i, k) * W(6, i, k);
-        const double inv = (nr > 0.0 && nr < 1e300) ? 1.0 / sqrt(nr) : 0.0;
-        for (int i = 0; i < n; ++i) W(5, i, k) = W(6, i, k) * inv;
+        for (int i = 0; i < n; ++i) Z(i, k) = (i >= r0 && i < r1) ? W(5, i, k) : 0.0;
       }
-      for (int i = 0; i < n; ++i) Z(i, k) = W(5, i, k);
+      __syncthreads();
     }
-    __syncthreads();
-    // Gram-Schmidt (two passes, whole workgroup) of each member against the
-    // earlier members and against every vector whose eigenvalue lies within
-    // a relative gap of 1e-3 of the cluster (their twisted vectors may
-    // overlap the members' inverse-iteration vectors).
     double* dots = buf + 6144;  // <= 1024 coefficients
     double* gsp = buf + 7168;   // NT partial sums
-    auto near = [&](int a, int b) {
-      const double ma = mu[n - 1 - a], mb = mu[n - 1 - b];
-      return fabs(ma - mb) <= 1e-3 * fmax(fabs(ma), fabs(mb));
+    int* refs = reinterpret_cast<int*>(buf + 5120);  // <= 1024 reference indices
+    // z_j -= sum_t (z_refs[t] . z_j) z_refs[t], then z_j / |z_j|; passes
+    // of classical Gram-Schmidt against the nref vectors listed in refs
+    auto gram_schmidt = [&](int j, int nref, int passes) {
+      for (int pass = 0; pass < passes; ++pass) {
+        // dots[t] = z_p(t) . z_j: 256 references at a time, the rows split
+        // over four thread groups (partial sums in LDS, added in a fixed
+        // order); rows of Z are contiguous in the vector index
+        const int rows_per = (n + 3) >> 2;
+        for (int c0 = 0; c0 < nref; c0 += 256) {
+          const int t = c0 + (tid & 255), g = tid >> 8;
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          if (t < nref) {
+            const int p = refs[t];
+            const int i0 = g * rows_per, i1 = min(n, i0 + rows_per);
+            int i = i0;
+            for (; i + 3 < i1; i += 4) {
+              a0 += Z(i, p) * Z(i, j);
+              a1 += Z(i + 1, p) * Z(i + 1, j);
+              a2 += Z(i + 2, p) * Z(i + 2, j);
+              a3 += Z(i + 3, p) * Z(i + 3, j);
+            }
+            for (; i < i1; ++i) a0 += Z(i, p) * Z(i, j);
+          }
+          gsp[tid] = (a0 + a1) + (a2 + a3);
+          __syncthreads();
+          if (tid < 256 && c0 + tid < nref) dots[c0 + tid] = ((gsp[tid] + gsp[256 + tid]) + gsp[512 + tid]) + gsp[768 + tid];
+          __syncthreads();
+        }
+        // z_j -= sum_t dots[t] z_p(t): four lanes per row, combined by shuffles
+        double part = 0.0;
+        const int q = tid & 3;
+        for (int i = tid >> 2; i < n; i += NT >> 2) {
+          double s0 = 0.0, s1 = 0.0;
+          int t = q;
+          for (; t + 4 < nref; t += 8) {
+            s0 += dots[t] * Z(i, refs[t]);
+            s1 += dots[t + 4] * Z(i, refs[t + 4]);
+          }
+          for (; t < nref; t += 4) s0 += dots[t] * Z(i, refs[t]);
+          double sum = s0 + s1;
+          sum += __shfl_xor(sum, 1, 64);
+          sum += __shfl_xor(sum, 2, 64);
+          const double zi = Z(i, j) - sum;
+          if (q == 0) {
+            Z(i, j) = zi;
+            part += zi * zi;
+          }
+        }
+        const double nr = block_sum(part, red);
+        const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+        for (int i = tid; i < n; i += NT) Z(i, j) *= inv;
+        __syncthreads();
+      }
     };
     for (int k = 0; k < nres; ++k) {
-      if (k > 0 && same(k - 1, k)) continue;  // not a cluster start
-      int e = k + 1;
-      while (e < nres && same(e - 1, e)) ++e;
-      const bool nz = is_noise(e - 1);  // the cluster reaches the noise level
-      if (e - k < 2 && !nz) continue;
-      int na = k, nb = e;
-      if (nz) {
+      if (is_noise(k)) {
+        if (k > 0 && is_noise(k - 1)) continue;  // not the start of the noise cluster
+        int e = k + 1;
+        while (e < nres && is_noise(e)) ++e;
         // the whole cluster at once against every other vector (two block
         // passes, coefficients C[t][c] in work array 7), then Gram-Schmidt
         // inside the cluster only
@@ -678,68 +843,33 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
           }
           __syncthreads();
         }
-      } else {
+        // the members are random vectors already projected off every other
+        // vector and well conditioned among themselves: one pass, the block
+        // Gram-Schmidt of stage 6 (or the caller's Cholesky pass) removes
+        // the second-order overlaps
+        for (int j = k; j < e; ++j) {
+          for (int t = tid; t < j - k; t += NT) refs[t] = k + t;
+          __syncthreads();
+          gram_schmidt(j, j - k, 1);
+        }
+        continue;
+      }
+      if (!is_member(k)) continue;
+      // references: the vectors of k's block within a relative gap of 1e-3
+      // that are final by now (earlier indices, and later ones that are
+      // not members); vectors of other blocks are orthogonal by support
+      if (tid == 0) {
+        int na = k, nb = k + 1;
         while (na > 0 && near(na - 1, k)) --na;
         while (nb < nres && near(nb, k)) ++nb;
+        const int bk = s_kb[n - 1 - k];
+        int c = 0;
+        for (int i = na; i < nb && c < 1024; ++i)
+          if (i != k && s_kb[n - 1 - i] == bk && !is_noise(i) && (i < k || !is_member(i))) refs[c++] = i;
+        s_nref = c;
       }
-      for (int j = nz ? k : k + 1; j < e; ++j) {
-        // reference vectors: [na, j) and [e, nb)
-        const int r1 = j - na, nref = r1 + (nb - e);
-        // the null-space members are random vectors already projected off
-        // every other vector and well conditioned among themselves: one
-        // pass, the block Gram-Schmidt of stage 6 (or the caller's Cholesky
-        // pass) removes the second-order overlaps
-        for (int pass = 0; pass < (nz ? 1 : 2); ++pass) {
-          // dots[t] = z_p(t) . z_j: 256 references at a time, the rows split
-          // over four thread groups (partial sums in LDS, added in a fixed
-          // order); rows of Z are contiguous in the vector index
-          const int rows_per = (n + 3) >> 2;
-          for (int c0 = 0; c0 < nref; c0 += 256) {
-            const int t = c0 + (tid & 255), g = tid >> 8;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            if (t < nref) {
-              const int p = (t < r1) ? na + t : e + (t - r1);
-              const int i0 = g * rows_per, i1 = min(n, i0 + rows_per);
-              int i = i0;
-              for (; i + 3 < i1; i += 4) {
-                a0 += Z(i, p) * Z(i, j);
-                a1 += Z(i + 1, p) * Z(i + 1, j);
-                a2 += Z(i + 2, p) * Z(i + 2, j);
-                a3 += Z(i + 3, p) * Z(i + 3, j);
-              }
-              for (; i < i1; ++i) a0 += Z(i, p) * Z(i, j);
-            }
-            gsp[tid] = (a0 + a1) + (a2 + a3);
-            __syncthreads();
-            if (tid < 256 && c0 + tid < nref) dots[c0 + tid] = ((gsp[tid] + gsp[256 + tid]) + gsp[512 + tid]) + gsp[768 + tid];
-            __syncthreads();
-          }
-          // z_j -= sum_t dots[t] z_p(t): four lanes per row, combined by shuffles
-          double part = 0.0;
-          const int q = tid & 3;
-          for (int i = tid >> 2; i < n; i += NT >> 2) {
-            double s0 = 0.0, s1 = 0.0;
-            int t = q;
-            for (; t + 4 < nref; t += 8) {
-              s0 += dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
-              s1 += dots[t + 4] * Z(i, (t + 4 < r1) ? na + t + 4 : e + (t + 4 - r1));
-            }
-            for (; t < nref; t += 4) s0 += dots[t] * Z(i, (t < r1) ? na + t : e + (t - r1));
-            double sum = s0 + s1;
-            sum += __shfl_xor(sum, 1, 64);
-            sum += __shfl_xor(sum, 2, 64);
-            const double zi = Z(i, j) - sum;
-            if (q == 0) {
-              Z(i, j) = zi;
-              part += zi * zi;
-            }
-          }
-          const double nr = block_sum(part, red);
-          const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-          for (int i = tid; i < n; i += NT) Z(i, j) *= inv;
-          __syncthreads();
-        }
-      }
+      __syncthreads();
+      gram_schmidt(k, s_nref, 2);
     }
   }
 }

@@ -14,6 +14,7 @@
 #include "chain_kernels.h"
 #include "cholqr.h"
 #include "host_math.h"
+#include "tempo_kernels.h"
 
 using ptt::BathDev;
 using ptt::BondJob;
@@ -1657,11 +1658,279 @@ extern "C" void pt_tebd_batch_destroy(pt_tebd_batch_t b) {
   delete b;
 }
 
+// ================================================= PT-MPO builds on the GPU
+namespace {
+// coupling eigenbasis of a d = 2 Hermitian operator: eigenvalues, the
+// eigenvector matrix, and whether the operator is already diagonal
+bool coupling_basis(const double* op, std::vector<double>& sigma, std::vector<cplx>& u, bool& diag) {
+  cplx s[4];
+  for (int i = 0; i < 4; ++i) s[i] = {op[2 * i], op[2 * i + 1]};
+  if (std::abs(s[1] - std::conj(s[2])) > 1e-12 || std::abs(s[0].imag()) > 1e-12 || std::abs(s[3].imag()) > 1e-12)
+    return false;
+  diag = std::abs(s[1]) == 0.0 && std::abs(s[2]) == 0.0;
+  u.assign(4, 0.0);
+  if (diag) {
+    sigma = {s[0].real(), s[3].real()};
+    u[0] = u[3] = 1.0;
+  } else {
+    double w[2];
+    ptt::heev(2, s, w, u.data());
+    sigma = {w[0], w[1]};
+  }
+  return true;
+}
+
+// P_k in the coupling eigenbasis ([e][e'][x]) -> the bath struct's layout:
+// unchanged when the coupling is diagonal, else W P W^-1 with W = U (x) U*
+// on the Liouville index ([e][e'][s_out][s_in])
+void fill_bath(int n_steps, const std::vector<int>& dims, const std::vector<std::vector<cplx>>& tens, bool diag,
+               const std::vector<cplx>& u, pt_tebd_bath* out) {
+  out->site = 0;
+  out->n_steps = n_steps;
+  out->diagonal = diag ? 1 : 0;
+  int32_t* bd = static_cast<int32_t*>(std::malloc(sizeof(int32_t) * (n_steps + 1)));
+  const double** tp = static_cast<const double**>(std::malloc(sizeof(double*) * n_steps));
+  for (int k = 0; k <= n_steps; ++k) bd[k] = dims[k];
+  cplx wmat[16];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k)
+        for (int l = 0; l < 2; ++l) wmat[(i * 2 + j) * 4 + (k * 2 + l)] = u[i * 2 + k] * std::conj(u[j * 2 + l]);
+  for (int k = 0; k < n_steps; ++k) {
+    const int xa = dims[k], xb = dims[k + 1];
+    const size_t per = diag ? 4 : 16;
+    double* t = static_cast<double*>(std::malloc(sizeof(double) * 2 * per * xa * xb));
+    for (int e = 0; e < xa; ++e)
+      for (int f = 0; f < xb; ++f) {
+        const cplx* p = &tens[k][((size_t)e * xb + f) * 4];
+        if (diag) {
+          for (int x = 0; x < 4; ++x) {
+            t[2 * (((size_t)e * xb + f) * 4 + x)] = p[x].real();
+            t[2 * (((size_t)e * xb + f) * 4 + x) + 1] = p[x].imag();
+          }
+        } else {
+          for (int so = 0; so < 4; ++so)
+            for (int si = 0; si < 4; ++si) {
+              cplx acc = 0.0;
+              for (int x = 0; x < 4; ++x) acc += wmat[so * 4 + x] * p[x] * std::conj(wmat[si * 4 + x]);
+              const size_t q = (((size_t)e * xb + f) * 4 + so) * 4 + si;
+              t[2 * q] = acc.real();
+              t[2 * q + 1] = acc.imag();
+            }
+        }
+      }
+    tp[k] = t;
+  }
+  out->bond_dims = bd;
+  out->tensors = tp;
+  out->caps = nullptr;
+}
+}  // namespace
+
+extern "C" pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_bath_params* params, double dt,
+                                                   int32_t n_steps, int32_t mem_steps, double eps, int32_t xi_max,
+                                                   int32_t d, void* hip_stream, pt_tebd_bath* out) {
+  if (n_builds < 1 || !params || !out || d != 2 || n_steps < 1 || mem_steps < 0 || xi_max < 1 || xi_max > 256 ||
+      !(eps >= 0.0) || !(dt > 0.0))
+    return PT_TEBD_EINVAL;
+  const int K = mem_steps, M = n_steps, acap = 4 * xi_max;
+  const size_t slot = (size_t)acap * 4 * acap;
+  std::vector<std::vector<double>> sigmas(n_builds);
+  std::vector<std::vector<cplx>> us(n_builds);
+  std::vector<char> diag(n_builds);
+  std::vector<double2> bfac((size_t)n_builds * (K + 1) * 16);
+  for (int b = 0; b < n_builds; ++b) {
+    const pt_bath_params& P = params[b];
+    if (!P.coupling_op) return PT_TEBD_EINVAL;
+    bool dg = false;
+    if (!coupling_basis(P.coupling_op, sigmas[b], us[b], dg)) return PT_TEBD_EINVAL;
+    diag[b] = dg;
+    std::vector<cplx> eta;
+    std::string err;
+    if (!ptt::bath_eta(P.alpha, P.wc, P.cutoff_kind, P.temperature, dt, K, eta, err)) return PT_TEBD_EINVAL;
+    const std::vector<double>& sg = sigmas[b];
+    for (int dl = 0; dl <= K; ++dl)
+      for (int x = 0; x < 4; ++x)
+        for (int xp = 0; xp < 4; ++xp) {
+          const double spx = sg[x / 2], smx = sg[x % 2], spy = sg[xp / 2], smy = sg[xp % 2];
+          const cplx v = std::exp(-(spx - smx) * (eta[dl] * spy - std::conj(eta[dl]) * smy));
+          bfac[((size_t)b * (K + 1) + dl) * 16 + x * 4 + xp] = ptt::mk<double>(v.real(), v.imag());
+        }
+  }
+  // device memory of the builds (a host helper, not the per-step path)
+  Bump sz(nullptr);
+  // per build: the stage jobs, their eigensolver jobs, and the refinement of
+  // small singular values (rows of W^H M right to left, columns of M W left
+  // to right) with its own eigensolver jobs
+  struct Dev {
+    double2* bf;
+    ptt::TempoJob* jobs;
+    HeevJob *hrl, *hlr, *hrl_ref, *hlr_ref;
+    ptt::RefineJob *rrl, *rlr;
+  };
+  struct Host {
+    std::vector<ptt::TempoJob> jobs;
+    std::vector<HeevJob> hrl, hlr, hrl_ref, hlr_ref;
+    std::vector<ptt::RefineJob> rrl, rlr;
+  };
+  auto plan = [&](Bump& bp, Host* h, Dev& dv) {
+    dv.bf = bp.take<double2>(bfac.size());
+    dv.jobs = bp.take<ptt::TempoJob>(n_builds);
+    dv.hrl = bp.take<HeevJob>(n_builds);
+    dv.hlr = bp.take<HeevJob>(n_builds);
+    dv.hrl_ref = bp.take<HeevJob>(n_builds);
+    dv.hlr_ref = bp.take<HeevJob>(n_builds);
+    dv.rrl = bp.take<ptt::RefineJob>(n_builds);
+    dv.rlr = bp.take<ptt::RefineJob>(n_builds);
+    for (int b = 0; b < n_builds; ++b) {
+      ptt::TempoJob J{};
+      J.K = K; J.M = M; J.xi_cap = xi_max; J.acap = acap; J.eps = eps;
+      J.bfac = dv.bf ? dv.bf + (size_t)b * (K + 1) * 16 : nullptr;
+      J.slots = bp.take<double2>((size_t)(K + 1) * slot);
+      J.sa = bp.take<int>(K + 1);
+      J.sc = bp.take<int>(K + 1);
+      J.tmp = bp.take<double2>(slot);
+      J.g = bp.take<double2>((size_t)acap * acap);
+      J.w = bp.take<double2>((size_t)acap * acap);
+      J.p = bp.take<double2>((size_t)4 * acap * acap);
+      J.lam = bp.take<double>(acap);
+      J.s = bp.take<double>(acap);
+      J.perm = bp.take<int>(acap);
+      J.sd = bp.take<int>(ptt::TS_COUNT);
+      J.out = bp.take<double2>((size_t)M * xi_max * xi_max * 4);
+      J.out_dims = bp.take<int>(M + 1);
+      J.status = bp.take<int>(1);
+      double2* refl = bp.take<double2>((size_t)acap * acap);
+      double* tri = bp.take<double>(6 * (size_t)acap);
+      double* work = bp.take<double>(8 * (size_t)acap * acap);
+      double* z = bp.take<double>((size_t)acap * acap);
+      double2* rw = bp.take<double2>((size_t)acap * acap);     // block eigenvectors
+      double2* tp = bp.take<double2>((size_t)4 * acap * acap); // rotated block of p
+      double2* tv = bp.take<double2>((size_t)acap * acap);     // rotated block of w
+      int* blk = bp.take<int>(4);
+      if (h) {
+        h->jobs.push_back(J);
+        HeevJob H{};
+        H.a = J.g; H.lda = acap; H.n_ptr = J.sd + ptt::TS_N; H.w = J.lam; H.refl = refl; H.tri = tri;
+        H.work = work; H.z = z; H.n_cap = acap; H.nvec_out = J.sd + ptt::TS_KEEP; H.rule = ptt::RULE_FULL;
+        H.eps = 0.0; H.cap = 0; H.extra_tail = nullptr; H.rank_tol = 0.0; H.v = J.w; H.ldv = acap;
+        H.scale = ptt::SCALE_NONE; H.status = J.status; H.noise_cluster = 1; H.abs_ref = nullptr; H.abs_tol = 0.0;
+        h->hrl.push_back(H);
+        H.rule = ptt::RULE_FULL;
+        h->hlr.push_back(H);
+        // the block Gram matrix goes into g (free between the projection and
+        // the finishing kernels), its eigenvectors into rw
+        HeevJob HR = H;
+        HR.n_ptr = blk + 1; HR.nvec_out = blk + 2; HR.v = rw; HR.rule = ptt::RULE_FULL;
+        h->hrl_ref.push_back(HR);
+        h->hlr_ref.push_back(HR);
+        ptt::RefineJob R{};
+        R.blk = blk; R.G = J.g; R.ldg = acap; R.W = rw; R.ldw = acap; R.TP = tp; R.TV = tv; R.ldtv = acap;
+        R.V = J.w; R.ldv = acap; R.s = J.s; R.P = J.p; R.ldp_ptr = J.sd + ptt::TS_COLS;
+        R.len_cols = J.sd + ptt::TS_ROWS; R.len_rows = J.sd + ptt::TS_COLS;
+        // right to left: the keep rows of p = W^H M (a x (d^2 c)); W is a x keep
+        ptt::RefineJob RL = R;
+        RL.cols = 0; RL.n_ptr = J.sd + ptt::TS_KEEP; RL.nv_ptr = J.sd + ptt::TS_ROWS; RL.ldtp = 4 * acap;
+        h->rrl.push_back(RL);
+        // left to right: the columns of p = M W ((a d^2) x c); W is c x c
+        ptt::RefineJob LR = R;
+        LR.cols = 1; LR.n_ptr = J.sd + ptt::TS_COLS; LR.nv_ptr = J.sd + ptt::TS_COLS; LR.ldtp = acap;
+        h->rlr.push_back(LR);
+      }
+    }
+  };
+  Dev dv{};
+  plan(sz, nullptr, dv);
+  const size_t bytes = sz.off + 256;
+  void* ws = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) return PT_TEBD_ENOMEM;
+  Bump bp(ws);
+  Host hs;
+  plan(bp, &hs, dv);
+  std::vector<ptt::TempoJob>& jobs = hs.jobs;
+  ptt::TempoJob* jobs_dev = dv.jobs;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  auto up = [&](void* dst, const void* src, size_t b) {
+    return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = up(dv.bf, bfac.data(), bfac.size() * sizeof(double2)) &&
+            up(dv.jobs, jobs.data(), n_builds * sizeof(ptt::TempoJob)) &&
+            up(dv.hrl, hs.hrl.data(), n_builds * sizeof(HeevJob)) && up(dv.hlr, hs.hlr.data(), n_builds * sizeof(HeevJob)) &&
+            up(dv.hrl_ref, hs.hrl_ref.data(), n_builds * sizeof(HeevJob)) &&
+            up(dv.hlr_ref, hs.hlr_ref.data(), n_builds * sizeof(HeevJob)) &&
+            up(dv.rrl, hs.rrl.data(), n_builds * sizeof(ptt::RefineJob)) &&
+            up(dv.rlr, hs.rlr.data(), n_builds * sizeof(ptt::RefineJob));
+  // three levels of refinement, each resolving singular values four decades
+  // further below the largest one than the level before
+  Exec tx{};
+  tx.stream = st;
+  tx.refine_levels = 3;
+  tx.refine_tau = 1e-4;
+  for (int b = 0; b < n_builds && ok; ++b)
+    ok = hipMemsetAsync(jobs[b].status, 0, sizeof(int), st) == hipSuccess;
+  const int tiles = (4 * acap + ptt::GEMM_BM - 1) / ptt::GEMM_BM;
+  const dim3 gg(tiles, tiles, n_builds);
+  const int sb = (n_builds + 63) / 64;
+  for (int k = 1; k <= M && ok; ++k) {
+    ptt::k_tempo_begin<<<n_builds, 256, 0, st>>>(jobs_dev, k);
+    const int m = std::min(K, k - 1);
+    for (int i = 0; i < m; ++i) {  // right to left: site k - i = L Q
+      ptt::k_tempo_stage<<<sb, 64, 0, st>>>(jobs_dev, n_builds, k, i, 1);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_RL_GRAM);
+      launch_heev(st, dv.hrl, n_builds, acap);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_RL_PROJ);
+      run_refine(tx, dv.rrl, dv.hrl_ref, n_builds, acap, 4 * acap, acap);
+      ptt::k_tempo_rl_finish<<<n_builds, 256, 0, st>>>(jobs_dev);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_RL_PUSH);
+      ptt::k_tempo_push_copy<<<n_builds, 256, 0, st>>>(jobs_dev, 1);
+    }
+    for (int i = 0; i < m; ++i) {  // left to right: truncated SVD of site k - m + i
+      ptt::k_tempo_stage<<<sb, 64, 0, st>>>(jobs_dev, n_builds, k, i, 0);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_LR_GRAM);
+      launch_heev(st, dv.hlr, n_builds, acap);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_LR_PROJ);
+      run_refine(tx, dv.rlr, dv.hlr_ref, n_builds, 4 * acap, acap, acap);
+      ptt::k_tempo_lr_rule<<<n_builds, 256, 0, st>>>(jobs_dev);
+      ptt::k_tempo_gemm<<<gg, ptt::GEMM_THREADS, 0, st>>>(jobs_dev, ptt::TG_LR_PUSH);
+      ptt::k_tempo_push_copy<<<n_builds, 256, 0, st>>>(jobs_dev, 0);
+    }
+  }
+  if (ok) ptt::k_tempo_end<<<n_builds, 256, 0, st>>>(jobs_dev);
+  ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+  // results to the host
+  for (int b = 0; b < n_builds && ok; ++b) {
+    std::vector<int> dims(M + 1);
+    int status = 0;
+    std::vector<double2> o((size_t)M * xi_max * xi_max * 4);
+    ok = hipMemcpy(dims.data(), jobs[b].out_dims, (M + 1) * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+         hipMemcpy(&status, jobs[b].status, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+         hipMemcpy(o.data(), jobs[b].out, o.size() * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) break;
+    if (status & 4) { ok = false; break; }
+    std::vector<std::vector<cplx>> tens(M);
+    for (int k = 0; k < M; ++k) {
+      const int xa = dims[k], xb = dims[k + 1];
+      tens[k].resize((size_t)xa * xb * 4);
+      for (size_t q = 0; q < tens[k].size(); ++q) {
+        const double2 v = o[(size_t)k * xi_max * xi_max * 4 + q];
+        tens[k][q] = {v.x, v.y};
+      }
+    }
+    fill_bath(M, dims, tens, diag[b] != 0, us[b], &out[b]);
+  }
+  (void)hipFree(ws);
+  return ok ? PT_TEBD_OK : PT_TEBD_EDEVICE;
+}
+
 // ------------------------------------------------------------ test hooks
 #include "pt_tebd_testing.h"
 
-extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
-                                       double* w, double* v, int32_t* nvec) {
+namespace {
+// pt_test_heev and pt_test_heev_tridiagonal: the eigensolver on one matrix;
+// tri (2 n doubles: diagonal, off-diagonal of T) and z (n x n, the
+// eigenvectors of T, row-major) are copied out when given
+pt_tebd_status test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap, double* w, double* v,
+                         int32_t* nvec, double* tri, double* z) {
   if (n < 1 || n > 1024 || !a || !w || !v || !nvec) return PT_TEBD_EINVAL;
   const size_t nn = (size_t)n * n;
   double2 *da = nullptr, *drefl = nullptr, *dv = nullptr;
@@ -1694,12 +1963,26 @@ extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule,
            hipMemcpy(w, dw, n * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
            hipMemcpy(v, dv, nn * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess &&
            hipMemcpy(nvec, dnvec, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
+      if (ok && tri) ok = hipMemcpy(tri, dtri, 2 * n * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
+      if (ok && z) ok = hipMemcpy(z, dz, nn * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
     }
   }
   if (!ok) st = PT_TEBD_EDEVICE;
   hipFree(da); hipFree(drefl); hipFree(dv); hipFree(dw); hipFree(dtri); hipFree(dwork); hipFree(dz);
   hipFree(dextra); hipFree(dn); hipFree(dnvec); hipFree(dstat); hipFree(djob);
   return st;
+}
+}  // namespace
+
+extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
+                                       double* w, double* v, int32_t* nvec) {
+  return test_heev(n, a, rule, eps, cap, w, v, nvec, nullptr, nullptr);
+}
+
+extern "C" pt_tebd_status pt_test_heev_tridiagonal(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
+                                                   double* w, double* v, int32_t* nvec, double* tri, double* z) {
+  if (!tri || !z) return PT_TEBD_EINVAL;
+  return test_heev(n, a, rule, eps, cap, w, v, nvec, tri, z);
 }
 
 // ------------------------------------------------------- no-alloc variant

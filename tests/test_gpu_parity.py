@@ -127,6 +127,86 @@ def test_heev_full_rule_rounded_null_space(n, rank, scale):
     assert np.abs(a @ v - v * w).max() < 1e-12 * scale
 
 
+def _check_full(a, w, v, nv, tol=1e-12):
+    n = a.shape[0]
+    assert nv == n
+    ref = np.sort(np.linalg.eigvalsh(a))[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() < 1e-13 * scale * n
+    assert np.abs(v.conj().T @ v - np.eye(n)).max() < tol
+    assert np.abs(a @ v - v * w).max() < tol * scale
+
+
+@pytest.mark.parametrize("phases", [False, True])
+def test_heev_exact_pairs_across_split_blocks(phases):
+    # a diagonal entry equal to an eigenvalue of the rest of the matrix and
+    # coupled to it far below the rounding level of |A| (4 is an eigenvalue
+    # of [[3, 1], [1, 3]]), next to blocks whose spectra repeat exactly
+    # (I_2 x C): the tridiagonal form splits into blocks that share
+    # eigenvalues to the last bit, and every eigenvector must still come out
+    # orthonormal with a rounding-level residual
+    print(f"heev split blocks phases={phases}", flush=True)
+    rng = np.random.default_rng(11)
+    t = 1e-16
+    core = np.array([[4.0, t, 0.0], [t, 3.0, 1.0], [0.0, 1.0, 3.0]], dtype=np.complex128)
+    c = rng.normal(size=(5, 5)) + 1j * rng.normal(size=(5, 5))
+    c = c @ c.conj().T
+    blocks = [core, np.kron(np.eye(2), c), np.array([[4.0]]), np.kron(np.eye(3), np.array([[2.0, 1.0], [1.0, 2.0]]))]
+    n = sum(b.shape[0] for b in blocks)
+    a = np.zeros((n, n), dtype=np.complex128)
+    o = 0
+    for b in blocks:
+        a[o:o + b.shape[0], o:o + b.shape[0]] = b
+        o += b.shape[0]
+    if phases:
+        d = np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+        a = (d[:, None] * a) * d.conj()[None, :]
+    for rule in (4, 3):
+        w, v, nv = _heev(n, a, rule=rule, eps=1e-28 if rule == 3 else 0.0)
+        _check_full(a, w, v, nv)
+
+
+@pytest.mark.parametrize("m", [6, 50, 128])
+def test_heev_doubly_degenerate_spectrum(m):
+    # Q (I_2 x C) Q^H: every eigenvalue exactly twice (the Gram matrices of
+    # states with a two-fold symmetry look like this); the tridiagonal form
+    # splits where the Krylov space of the first column closes
+    print(f"heev doubly degenerate m={m}", flush=True)
+    rng = np.random.default_rng(100 + m)
+    c = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+    c = c @ c.conj().T
+    q, _ = np.linalg.qr(rng.normal(size=(2 * m, 2 * m)) + 1j * rng.normal(size=(2 * m, 2 * m)))
+    a = q @ np.kron(np.eye(2), c) @ q.conj().T
+    a = np.triu(a) + np.triu(a, 1).conj().T
+    w, v, nv = _heev(2 * m, a, rule=4)
+    _check_full(a, w, v, nv)
+
+
+@pytest.mark.parametrize("seed", [203, 206, 207])
+def test_heev_close_pairs_inside_one_block(seed):
+    # a graded tridiagonal block (eigenvalues over twelve decades) joined
+    # to its mirror image by a coupling just above the splitting threshold:
+    # one unreduced block whose eigenvalues come in pairs equal to ~1e-16,
+    # as in the Gram matrices of the PT-MPO construction.  Inverse iteration
+    # for the second member of each pair must not collapse onto the first.
+    import scipy.linalg
+    print(f"heev close pairs seed={seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    m = 18
+    lam = 10.0 ** (-12 * np.arange(m) / (m - 1)) * 1e11
+    q, _ = np.linalg.qr(rng.normal(size=(m, m)))
+    h = scipy.linalg.hessenberg((q * lam) @ q.T)
+    db, eb = np.diag(h).copy(), np.diag(h, 1).copy()
+    tn = np.abs(h).sum(1).max()
+    dd = np.concatenate([db, db[::-1]])
+    ee = np.concatenate([eb, [3.0 * 2.2e-16 * tn], eb[::-1]])
+    t = np.diag(dd) + np.diag(ee, 1) + np.diag(ee, -1)
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 2 * m))
+    a = (ph[:, None] * t) * ph.conj()[None, :]
+    w, v, nv = _heev(2 * m, a, rule=4)
+    _check_full(a, w, v, nv)
+
+
 def test_gates_match_oracle():
     wl = W.random_small_chain(3, 5)
     wl["lindblad"] = [[0.2 * SZ], [], [0.1 * (SX - 1j * SY) / 2], [], [0.3 * SX]]
