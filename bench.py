@@ -5,14 +5,20 @@ One step = one full time step Delta t of the chain (Sec. II, the step of
 eq. propagator-env: two chain half-steps of three Trotter sublayers of
 two-site updates, and the absorption of every bath's PT-MPO tensor in
 between) followed by one read-out of <sigma^z_n> on every site.  A
-site-update is one site advanced by one Delta t, so a run of K steps of an
-N-site chain counts N*K site-updates.
+site-update is one site advanced by one Delta t, so K steps of an N-site
+chain count N*K site-updates.
 
 Default workload: the N = 21 XY chain with a bath on every site (chi <= 64,
-xi <= 24, dt = 0.1, 100 steps).  The timed region runs the workload's steps
-1..K from the initial state on a fresh handle, inputs and PT-MPOs already
-resident in device memory; gate build and PT-MPO build/upload are timed
-separately and excluded.
+xi <= 24, dt = 0.1, 100 steps), run twice on fresh handles over the same
+window, steps 1..K from the initial state (K = 100, the whole workload, by
+default): once in the FP32-mixed form (complex contractions in single
+precision on the matrix cores, eigensolvers, singular values, gates, PT
+absorption and the log-scale in double precision) and once in plain FP64.
+The headline value is the FP32-mixed rate; the FP64 rate, the speed-up,
+each form's largest deviation from the stored oracle trajectory and the
+per-step latency quantiles sit beside it.  Inputs and PT-MPOs are resident
+in device memory when the timed region starts; the PT-MPO build (on the
+GPU) and handle creation are timed separately and excluded.
 
 Prints one JSON line.
 """
@@ -29,41 +35,40 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 METRIC = "site-updates/s, XY N=21 chi=64, FP32-mixed vs FP64 at <=1e-4 err; p50/p99 latency"
+# MI355X published dense peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32_mixed": 157.3}
+PROFILES = os.path.join(ROOT, "profiles")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+KERNEL_CLASS = {"none": 0, "eigensolver": 1, "gemm": 2}
 
 
 def parse():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=100, help="timed steps (the workload has 100)")
-    p.add_argument("--warmup", type=int, default=3, help="untimed steps on a throwaway handle")
+    p.add_argument("--steps", type=int, default=100, help="timed steps from the initial state (the workload has 100)")
+    p.add_argument("--warmup", type=int, default=2, help="untimed steps on a throwaway handle per form")
     p.add_argument("--workload", default="xy21")
-    p.add_argument("--precision", default="fp64", choices=["fp64"])
-    p.add_argument("--cpu-seconds", type=float, default=20.0,
-                   help="time budget of the oracle CPU baseline (0 disables it)")
-    p.add_argument("--chains", type=int, default=1,
-                   help="independent copies of the workload, each on a stream of its own (value = their total)")
+    p.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_mixed"],
+                   help="forms to run; with both, value is the FP32-mixed rate")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="time budget of each oracle CPU baseline run (1 thread, all cores; 0 disables them)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="before the workload, run one element-wise copy kernel that reads and writes MIB MiB "
                         "(the reference for hardware byte counters)")
     p.add_argument("--kernel", default="eigensolver", choices=["eigensolver", "gemm", "none"],
-                   help="kernel class timed per launch with HIP events during the timed region "
+                   help="kernel class timed per launch with HIP events during the headline form's timed region "
                         "(the dominant one) for the roofline object")
     return p.parse_args()
 
 
-KERNEL_CLASS = {"none": 0, "eigensolver": 1, "gemm": 2}
-# MI355X published peaks
-PEAK_FP64_TFLOPS = 78.6   # FP64 vector and FP64 dense matrix
-PROFILES = os.path.join(ROOT, "profiles")
-
-
 def kernel_sources(kind):
     csrc = os.path.join(ROOT, "paper_2201_05529_amd", "csrc")
-    files = {"eigensolver": ["heev.h", "device_common.h"], "gemm": ["gemm.h", "bond_kernels.h", "device_common.h"]}
+    files = {"eigensolver": ["heev.h", "device_common.h"], "gemm": ["gemm.h", "gemm_mfma.h", "bond_kernels.h",
+                                                                  "device_common.h"]}
     return [os.path.join(csrc, f) for f in files[kind]]
 
 
-def traffic_from_profiles(kind, launches_per_step):
+def traffic_from_profiles(kind):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources (else None)."""
     import hashlib
@@ -81,66 +86,176 @@ def traffic_from_profiles(kind, launches_per_step):
     return rec.get("bytes_per_launch")
 
 
-def roofline(kind, ms_total, launches, flops):
+def kernel_roofline(kind, ms_total, launches, flops):
+    """The dominant kernel alone: algorithmic flops per launch / average
+    launch duration (HIP events on the handle's stream)."""
     if kind == "none" or launches == 0 or ms_total <= 0.0:
         return None
     avg_s = ms_total * 1e-3 / launches
     achieved = flops / launches / avg_s * 1e-12
-    bound = "alu"  # both kernels run FP64 vector arithmetic (CDNA4 has no faster FP64 matrix rate)
-    return {"bound": bound, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profiles(kind, launches),
+    peak = PEAK_TFLOPS["fp64"]  # the eigensolver runs FP64 vector arithmetic in both forms
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic_from_profiles(kind),
             "kernel": {"eigensolver": "heev_solve_kernel", "gemm": "k_bond_gemm"}[kind],
-            "launches": launches, "avg_launch_ms": ms_total / launches,
-            "alg_flops_per_launch": flops / launches}
+            "launches": launches, "avg_launch_ms": ms_total / launches, "alg_flops_per_launch": flops / launches}
+
+
+def composite_roofline(model_flops, elapsed_s, precision):
+    """The whole step: T_ideal = (F_a1 + F_a2 + F_a3 + F_a4) / matrix-core peak
+    of the form's contraction type, against the measured time."""
+    f = float(np.sum(model_flops))
+    peak = PEAK_TFLOPS[precision] * 1e12
+    t_ideal = f / peak
+    return {"model_flops": f, "F_a1_a4": [float(x) for x in model_flops], "peak_tflops": PEAK_TFLOPS[precision],
+            "achieved_tflops": f / elapsed_s * 1e-12, "t_ideal_s": t_ideal, "t_measured_s": elapsed_s,
+            "frac": t_ideal / elapsed_s}
 
 
 def library_baths(wl, n_steps):
-    """PT-MPOs from the library's own builder (one per distinct parameter set)."""
+    """PT-MPOs from the library's GPU builder, one per distinct parameter set."""
     from paper_2201_05529_amd import binding as B
-    cache, out = {}, []
+    keys, params = [], []
     for b in wl["baths"]:
         key = (b["alpha"], b["wc"], b["temperature"], b["k_cut"], b["cutoff"], b["coupling_op"].tobytes())
-        if key not in cache:
-            cache[key] = B.build_ptmpo(b["alpha"], b["wc"], b["temperature"], wl["dt"], n_steps, b["k_cut"],
-                                       wl["eps_tempo"], wl["xi_max"], b["coupling_op"], cutoff=b["cutoff"])
-        out.append({"site": b["site"], "tensors": cache[key]["tensors"]})
+        if key not in keys:
+            keys.append(key)
+            params.append(b)
+    built = {}
+    by_k = {}
+    for key, b in zip(keys, params):
+        by_k.setdefault(b["k_cut"], []).append((key, b))
+    for k_cut, items in by_k.items():
+        pts = B.build_ptmpo_batch([{"alpha": b["alpha"], "wc": b["wc"], "temperature": b["temperature"],
+                                    "coupling_op": b["coupling_op"], "cutoff": b["cutoff"]} for _, b in items],
+                                  wl["dt"], n_steps, k_cut, wl["eps_tempo"], wl["xi_max"])
+        for (key, _), pt in zip(items, pts):
+            built[key] = pt
+    out = []
+    for b in wl["baths"]:
+        key = (b["alpha"], b["wc"], b["temperature"], b["k_cut"], b["cutoff"], b["coupling_op"].tobytes())
+        out.append({"site": b["site"], "tensors": built[key]["tensors"]})
     return out
 
 
-def make_chain(wl, baths, stream=None):
+def make_chain(wl, baths, precision):
     from paper_2201_05529_amd import binding as B
+    prec = B.FP32_MIXED if precision == "fp32_mixed" else B.FP64
     return B.Chain(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths, chi_max=wl["chi_max"],
-                   xi_max=wl["xi_max"], eps=wl["eps"], lindblad=wl.get("lindblad"), stream=stream)
+                   xi_max=wl["xi_max"], eps=wl["eps"], lindblad=wl.get("lindblad"), precision=prec)
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, f"{name}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    sz = np.array(g["sz_re"]) + 1j * np.array(g["sz_im"])
+    tr = np.array(g["trace_re"]) + 1j * np.array(g["trace_im"])
+    spread = None
+    sp = os.path.join(GOLDEN, f"{name}_spread.json")
+    if os.path.exists(sp):
+        with open(sp) as f:
+            spread = np.array(json.load(f)["sz"])
+    return sz, tr, spread
+
+
+def run_form(wl, baths, precision, args, timed_kernel):
+    import torch
+    n = wl["n_sites"]
+    sites = np.arange(n, dtype=np.int32)
+    from paper_2201_05529_amd import workloads as W
+    ops = np.array([W.SZ] * n)
+    if args.warmup > 0:
+        ch = make_chain(wl, baths, precision)
+        for _ in range(args.warmup):
+            ch.step(1)
+            ch.observe(sites, ops)
+        ch.close()
+    t0 = time.perf_counter()
+    ch = make_chain(wl, baths, precision)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    ch.kernel_timing(KERNEL_CLASS[timed_kernel])
+    ch.model_flops(reset=True)
+    torch.cuda.synchronize()
+    sz, tr, lat = [], [], []
+    peak_chi = peak_xi = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        ch.step(1)
+        vals, trace = ch.observe(sites, ops)   # copies to the host: the step has finished
+        lat.append(time.perf_counter() - ts)
+        sz.append(vals)
+        tr.append(trace)
+        if (k + 1) % 20 == 0:
+            print(f"bench[{precision}]: step {k + 1}/{args.steps} {time.perf_counter() - t0:.2f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    chi, xi = ch.bond_dims()
+    peak_chi, peak_xi = int(chi.max()), int(xi.max())
+    ms_k, launches_k, flops_k = ch.kernel_timing_read()
+    mf = ch.model_flops()
+    ch.close()
+    lat = np.array(lat) * 1e3
+    return {"value": n * args.steps / elapsed, "elapsed_s": elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+            "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                "max": float(lat.max())},
+            "create_s": t_create, "peak_chi": peak_chi, "peak_xi": peak_xi,
+            "sz": np.array(sz), "trace": np.array(tr), "kernel": (ms_k, launches_k, flops_k), "model_flops": mf}
+
+
+def errors_vs_golden(res, golden, steps):
+    if golden is None:
+        return None
+    gsz, gtr, spread = golden
+    k = min(steps, gsz.shape[0] - 1)
+    e_sz = np.abs(res["sz"][:k] - gsz[1:k + 1]).max(axis=1)
+    e_tr = np.abs(res["trace"][:k] - gtr[1:k + 1])
+    out = {"steps_compared": k, "max_dsz": float(e_sz.max()), "max_dtrace": float(e_tr.max()),
+           "max_dsz_steps_1_20": float(e_sz[:20].max()), "max_dtrace_steps_1_20": float(e_tr[:20].max())}
+    if spread is not None:
+        m = min(k, len(spread) - 1)
+        out["oracle_spread_sz_steps_1_%d" % m] = float(np.max(spread[1:m + 1]))
+    return out
 
 
 def cpu_baseline(wl, seconds):
     """The oracle (FP64 NumPy) on the host, steps 1..S of the same workload
-    until the time budget is spent (at least one step)."""
+    from the initial state until the time budget is spent (at least one
+    step), once with one BLAS thread and once with every host core."""
     from oracle import pt_tebd
     from oracle.build import problem_from_workload
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
     n = wl["n_sites"]
     prob, _ = problem_from_workload(wl, n_steps=wl["n_steps"])
-    eng = pt_tebd.Engine(prob)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        eng.step(1)
-        for s in range(n):
-            eng.expectation(s, np.array([[1, 0], [0, -1]], dtype=np.complex128))
-        steps += 1
-        t = time.perf_counter() - t0
-        if t >= seconds or steps >= wl["n_steps"]:
-            break
-    chi = max(eng.mps.bond_dims())
-    return {"value": n * steps / t, "unit": "site-updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"steps 1..{steps} of the {wl['n_steps']}-step workload from the initial state "
-                      f"(max chi reached {chi}; later steps at chi={wl['chi_max']} cost more), "
-                      f"{t:.1f} s wall"}
+    sz_op = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+    def run():
+        eng = pt_tebd.Engine(prob)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            eng.step(1)
+            for s in range(n):
+                eng.expectation(s, sz_op)
+            steps += 1
+            t = time.perf_counter() - t0
+            if t >= seconds or steps >= wl["n_steps"]:
+                return steps, t, max(eng.mps.bond_dims())
+
+    all_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        s1, t1, chi1 = run()
+    sa, ta, chia = run()
+    return {"value": n * sa / ta, "unit": "site-updates/s", "cores": int(all_threads), "kind": "oracle",
+            "sample": f"steps 1..{sa} of the {wl['n_steps']}-step workload from the initial state (max chi reached "
+                      f"{chia}; the GPU window runs further, to chi={wl['chi_max']}, where a step costs more), "
+                      f"{ta:.1f} s wall, NumPy/LAPACK with {all_threads} BLAS threads",
+            "value_1_thread": n * s1 / t1,
+            "sample_1_thread": f"steps 1..{s1}, {t1:.1f} s wall, one BLAS thread"}
 
 
 def main():
@@ -170,69 +285,52 @@ def main():
     horizon = max(args.steps, args.warmup, wl["n_steps"])
     t0 = time.perf_counter()
     baths = library_baths(wl, horizon)
+    torch.cuda.synchronize()
     t_ptmpo = time.perf_counter() - t0
-    sites = np.arange(n, dtype=np.int32)
-    ops = np.array([W.SZ] * n)
-
-    # warm-up on a throwaway handle
-    if args.warmup > 0:
-        ch = make_chain(wl, baths)
-        for _ in range(args.warmup):
-            ch.step(1)
-            ch.observe(sites, ops)
-        ch.close()
-        del ch
-
-    t0 = time.perf_counter()
-    n_chains = max(1, args.chains)
-    # one chain on the current stream; further copies on streams of their
-    # own (default priority), so their launches overlap on the device
-    streams = [None] + [torch.cuda.Stream() for _ in range(n_chains - 1)]
-    chains = [make_chain(wl, baths, stream=st) for st in streams]
-    ch = chains[0]
-    torch.cuda.synchronize()
-    t_create = time.perf_counter() - t0
-    ch.kernel_timing(KERNEL_CLASS[args.kernel])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    peak_chi, peak_xi = 0, 0
-    for k in range(args.steps):
-        for c in chains:
-            c.step(1)
-        for c in chains:
-            vals, tr = c.observe(sites, ops)
-        chi, xi = ch.bond_dims()
-        peak_chi, peak_xi = max(peak_chi, int(chi.max())), max(peak_xi, int(xi.max()))
-        if (k + 1) % 10 == 0:
-            print(f"bench: step {k + 1}/{args.steps} {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_k, launches_k, flops_k = ch.kernel_timing_read()
-    value = n_chains * n * args.steps / elapsed
+    forms = ["fp32_mixed", "fp64"] if args.precision == "both" else [args.precision]
+    head = forms[0]
+    golden = load_golden(args.workload)
+    res = {}
+    for f in forms:
+        res[f] = run_form(wl, baths, f, args, args.kernel if f == head else "none")
+    r = res[head]
+    window = f"steps 1..{args.steps} from the initial state"
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": r["value"],
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c64-mfma+f64" if head == "fp32_mixed" else "c128",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: N={n} XY chain, a bath on every site, chi<={wl['chi_max']}, "
-                               f"xi<={wl['xi_max']}, dt={wl['dt']}, steps 1..{args.steps}, FP64 plain"
-                               + (f", {n_chains} independent copies on {n_chains} streams" if n_chains > 1 else ""),
-                   "precision": args.precision, "peak_chi": peak_chi, "peak_xi": peak_xi,
-                   "trace": [tr.real, tr.imag], "ptmpo_build_s": t_ptmpo, "create_s": t_create},
+        "config": {"workload": f"{args.workload}: N={n} chain, {len(wl['baths'])} ohmic bath(s), chi<={wl['chi_max']}, "
+                               f"xi<={wl['xi_max']}, dt={wl['dt']}, {window}; value = {head} form",
+                   "forms": forms, "ptmpo_build_s": t_ptmpo, "ptmpo_builder": "GPU (pt_mpo_build_ohmic_batch)"},
     }
-    rl = roofline(args.kernel, ms_k, launches_k, flops_k)
+    for f in forms:
+        rf = res[f]
+        out["config"][f] = {
+            "site_updates_per_s": rf["value"], "ms_per_step": rf["ms_per_step"],
+            "step_latency_ms": rf["step_latency_ms"], "create_s": rf["create_s"],
+            "peak_chi": rf["peak_chi"], "peak_xi": rf["peak_xi"],
+            "trace_final": [float(rf["trace"][-1].real), float(rf["trace"][-1].imag)],
+            "error_vs_oracle": errors_vs_golden(rf, golden, args.steps),
+            "composite_roofline": composite_roofline(rf["model_flops"], rf["elapsed_s"], f),
+        }
+    if len(forms) == 2:
+        out["config"]["speedup_fp32_mixed_vs_fp64"] = res["fp32_mixed"]["value"] / res["fp64"]["value"]
+        out["config"]["max_dsz_fp32_mixed_vs_fp64"] = float(np.abs(res["fp32_mixed"]["sz"] - res["fp64"]["sz"]).max())
+    out["p50_ms"] = r["step_latency_ms"]["p50"]
+    out["p99_ms"] = r["step_latency_ms"]["p99"]
+    rl = kernel_roofline(args.kernel, *r["kernel"])
     if rl is not None:
         out["roofline"] = rl
-    for c in chains:
-        c.close()
+        out["roofline"]["composite_frac"] = out["config"][head]["composite_roofline"]["frac"]
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -142,6 +142,20 @@ pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a
  * NULL).  Syncs. */
 pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi);
 
+/* Minimal algorithmic work of the bond updates stepped so far, from the run-
+ * time dims of every update (chi_{n-1}, xi_n, chi_n, xi_{n+1}, chi_{n+1},
+ * the ranks l, r of B_L, B_R and the new chi'), in flops with a complex
+ * multiply-add counted as 8 (Appendix A.2 (c)-(h)):
+ *   out[0] F_a1 = 16 (chi_{n-1} xi_n)(d^2 chi_n) l + 16 (d^2 chi_n)(xi_{n+1} chi_{n+1}) r
+ *               (rank-l / rank-r factorisations of B_L and B_R, two passes)
+ *   out[1] F_a2 = 8 (d^2 l) chi_n (d^2 r) + 8 d^8 l r   (X lambda Y and the gate)
+ *   out[2] F_a3 = 16 (d^2 l)(d^2 r) chi'                   (top-chi' part of D)
+ *   out[3] F_a4 = 8 (chi_{n-1} xi_n) l (d^2 chi') + 8 (d^2 chi') r (xi_{n+1} chi_{n+1})
+ *               (the two rebuild products)
+ * Counted on the device in each update's final kernel; reset != 0 clears
+ * the counters after the read.  Syncs. */
+pt_tebd_status pt_tebd_model_flops(pt_tebd_t h, double* out, int32_t reset);
+
 /* Host copy of the whole augmented state (Gamma, lambda, log-scale, step).
  * With buf = NULL only *bytes is set.  Syncs.  pt_tebd_restore loads it back
  * into a handle created from the same configuration: EINVAL (nothing is

@@ -32,6 +32,16 @@ pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps
 pt_tebd_status pt_test_heev_tridiagonal(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
                                         double* w, double* v, int32_t* nvec, double* tri, double* z);
 
+/* Stage times of the eigensolver on one matrix (rule as pt_test_heev),
+ * averaged over reps runs on fresh copies of a: stage_ms[0..5] the
+ * tridiagonal reduction, the shifted factorisation, the eigenvalues, the
+ * selection rule, the twisted eigenvectors and the cluster pass (device
+ * wall clock inside the kernel), stage_ms[6] the whole solve kernel and
+ * stage_ms[7] the back-transformation plus the two orthonormalisation
+ * passes (HIP events).  stage_ms holds 9 doubles ([8] is zero). */
+pt_tebd_status pt_test_heev_profile(int32_t n, const double* a, int32_t rule, double eps, int32_t reps,
+                                    double* stage_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,7 @@ def lib():
         L.pt_tebd_observe.argtypes = [vp, i32, ip, dp, dp, dp]
         L.pt_tebd_correlate.argtypes = [vp, i32, dp, i32, dp, i32, dp]
         L.pt_tebd_bond_dims.argtypes = [vp, ip, ip]
+        L.pt_tebd_model_flops.argtypes = [vp, dp, i32]
         L.pt_tebd_snapshot.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
         L.pt_tebd_restore.argtypes = [vp, vp, ctypes.c_size_t]
         L.pt_tebd_current_step.argtypes = [vp]
@@ -288,6 +289,13 @@ class Chain:
         self._check(lib().pt_tebd_bond_dims(self.handle, chi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                             xi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "bond_dims")
         return chi[:self.n_sites - 1].copy(), xi
+
+    def model_flops(self, reset=False):
+        """Minimal algorithmic flops F_a1..F_a4 of the bond updates so far
+        (pt_tebd_model_flops), as a length-4 array."""
+        out = np.zeros(4)
+        self._check(lib().pt_tebd_model_flops(self.handle, _dptr(out), 1 if reset else 0), "model_flops")
+        return out
 
     def snapshot(self):
         size = ctypes.c_size_t()

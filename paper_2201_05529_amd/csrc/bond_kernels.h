@@ -48,6 +48,7 @@ struct ChainDev {
   double* lam;           // [(n_sites + 1) * chi_cap]
   double* log_scale;     // [1]
   int* status;           // [1] sticky error bits
+  double* work;          // [4] model flops F_a1..F_a4 of the bond updates so far (see k_finalize)
 };
 
 __device__ inline double2* gamma_cur(const ChainDev& c, int site) {
@@ -736,6 +737,16 @@ __global__ void k_finalize(const ChainDev* chains, const BondJob* jobs) {
     if (es & EIG_SIZE) bad |= ST_RANGE;
     if (bad) atomicOr(C.status, bad);
     J.norms[3] = bad ? 0.0 : log(nrm) + J.norms[7];   // summed in item order by k_logscale
+    // minimal algorithmic work of this update from its dims (complex
+    // multiply-add = 8 flops, d^2 = 4): rank-l / rank-r factorisations of
+    // B_L, B_R (two passes each); the X lambda Y contraction and the 16 x 16
+    // gate; the top-chi' part of D (two passes); the two rebuild products
+    const double a = D[D_A], e = D[D_E], b = D[D_B], f = D[D_F], c = D[D_C];
+    const double l = D[D_L], r = D[D_R], cp = chi;
+    atomicAdd(C.work + 0, 16.0 * (a * e) * (4.0 * b) * l + 16.0 * (4.0 * b) * (f * c) * r);
+    atomicAdd(C.work + 1, 8.0 * (4.0 * l) * b * (4.0 * r) + 8.0 * 256.0 * l * r);
+    atomicAdd(C.work + 2, 16.0 * (4.0 * l) * (4.0 * r) * cp);
+    atomicAdd(C.work + 3, 8.0 * (a * e) * l * (4.0 * cp) + 8.0 * (4.0 * cp) * r * (f * c));
     C.chi[J.bond + 1] = chi;
     C.parity[J.bond] ^= 1;
     C.parity[J.bond + 1] ^= 1;

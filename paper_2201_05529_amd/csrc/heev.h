@@ -83,6 +83,7 @@ struct HeevJob {
   int noise_cluster; // 1: eigenvalues at the rounding level of zero form one cluster (stage 4b)
   const double* abs_ref;  // RULE_RANK: if set, also drop eigenvalues <= abs_tol * (*abs_ref),
   double abs_tol;         //            and allow no eigenpair at all
+  unsigned long long* stamps;  // if set: wall-clock stamps at the stage boundaries [8] (profiling)
 };
 
 constexpr int HEEV_THREADS = 256;          // back-transformation kernel
@@ -124,6 +125,10 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   }
   if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
   if (flops && tid == 0) atomicAdd(flops, 16.0 / 3.0 * (double)n * n * n);
+  auto stamp = [&](int i) {
+    if (J.stamps && tid == 0) J.stamps[i] = wall_clock64();
+  };
+  stamp(0);
   __shared__ double buf[8192];     // stage 1: two v, w, partial sums; later: d, l, l d, l^2 d, mu, tau
   __shared__ double red[NT / 64];
   __shared__ double2 s_tau;
@@ -278,6 +283,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     }
   }
   __syncthreads();
+  stamp(1);
 
   // -------- stage 2: T + delta I = L D L^T with D > 0
   double* d = buf;
@@ -327,6 +333,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     s_ok = ok;
   }
   __syncthreads();
+  stamp(2);
   const double tnorm = s_tnorm;
   const double delta = s_delta;
   if (!s_ok) {
@@ -438,6 +445,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     for (int j = tid; j < n; j += NT) J.w[n - 1 - j] = mu[j] - delta;
   }
   __syncthreads();
+  stamp(3);
 
   // -------- stage 3b: selection rule (thread 0)
   if (tid == 0) {
@@ -483,6 +491,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     *J.nvec_out = nvec;
   }
   __syncthreads();
+  stamp(4);
   const int nvec = s_nvec;
 
   // -------- stage 4: eigenvectors of T by twisted factorisations of
@@ -560,6 +569,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     }
   }
   __syncthreads();
+  stamp(5);
 
   // -------- stage 4b: clusters of numerically equal eigenvalues (relative
   // gap below 1e-9) inside one block.  Twisted vectors of equal mu
@@ -872,6 +882,8 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
       gram_schmidt(k, s_nref, 2);
     }
   }
+  __syncthreads();
+  stamp(6);
 }
 
 // --------------------------------------------------------------- stage 5

@@ -157,6 +157,7 @@ struct DevPtrs {
   double* lam[2];
   double* log_scale[2];
   int* status[2];
+  double* work[2];
   ChainDev* chains;
   double2* gates;
   BathDev* baths;
@@ -197,6 +198,7 @@ size_t layout(const Caps& c, const pt_tebd_config* cfg, const std::vector<long l
     P.lam[k] = bp.take<double>((size_t)(N + 1) * c.chi_cap);
     P.log_scale[k] = bp.take<double>(1);
     P.status[k] = bp.take<int>(1);
+    P.work[k] = bp.take<double>(4);
   }
   P.chains = bp.take<ChainDev>(2);
   P.timing_flops = bp.take<double>(4);
@@ -799,7 +801,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     ChainDev& C = h->chain_host[k];
     C.n_sites = N; C.chi_cap = c.chi_cap; C.xi_cap = c.xi_cap; C.gam_cap = c.gam_cap;
     C.gam = P.gam[k]; C.parity = P.parity[k]; C.chi = P.chi[k]; C.xi = P.xi[k];
-    C.lam = P.lam[k]; C.log_scale = P.log_scale[k]; C.status = P.status[k];
+    C.lam = P.lam[k]; C.log_scale = P.log_scale[k]; C.status = P.status[k]; C.work = P.work[k];
   }
   {
     std::vector<double2> g0((size_t)N * 2 * c.gam_cap, ptt::mk<double>(0.0, 0.0));
@@ -810,6 +812,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     std::vector<double> lam((size_t)(N + 1) * c.chi_cap, 0.0);
     for (int n = 0; n <= N; ++n) lam[(size_t)n * c.chi_cap] = 1.0;
     double zero = 0.0;
+    const double zw[4] = {0.0, 0.0, 0.0, 0.0};
     int zi = 0;
     bool ok = check(hipMemcpyAsync(P.gam[0], g0.data(), g0.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.parity[0], zeros.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
@@ -819,6 +822,8 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
               check(hipMemcpyAsync(P.log_scale[0], &zero, sizeof(double), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.status[0], &zi, sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.status[1], &zi, sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.work[0], zw, sizeof(zw), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.work[1], zw, sizeof(zw), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.chains, h->chain_host, 2 * sizeof(ChainDev), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipStreamSynchronize(st), hp, "init sync");
     if (!ok) return PT_TEBD_EDEVICE;
@@ -1138,6 +1143,22 @@ pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi) {
   if (xi)
     for (int n = 0; n < N; ++n) xi[n] = x[n];
   return device_status(h, 0);
+}
+
+pt_tebd_status pt_tebd_model_flops(pt_tebd_t h, double* out, int32_t reset) {
+  if (!h || !out) return PT_TEBD_EINVAL;
+  double w[4];
+  if (!check(hipMemcpyAsync(w, h->chain_host[0].work, sizeof(w), hipMemcpyDeviceToHost, h->stream), h, "work") ||
+      !check(hipStreamSynchronize(h->stream), h, "sync"))
+    return PT_TEBD_EDEVICE;
+  for (int i = 0; i < 4; ++i) out[i] = w[i];
+  if (reset) {
+    const double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!check(hipMemcpyAsync(h->chain_host[0].work, z, sizeof(z), hipMemcpyHostToDevice, h->stream), h, "work") ||
+        !check(hipStreamSynchronize(h->stream), h, "sync"))
+      return PT_TEBD_EDEVICE;
+  }
+  return PT_TEBD_OK;
 }
 
 namespace {
@@ -1977,6 +1998,75 @@ pt_tebd_status test_heev(int32_t n, const double* a, int32_t rule, double eps, i
 extern "C" pt_tebd_status pt_test_heev(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
                                        double* w, double* v, int32_t* nvec) {
   return test_heev(n, a, rule, eps, cap, w, v, nvec, nullptr, nullptr);
+}
+
+extern "C" pt_tebd_status pt_test_heev_profile(int32_t n, const double* a, int32_t rule, double eps, int32_t reps,
+                                               double* stage_ms) {
+  if (n < 1 || n > 1024 || !a || !stage_ms || reps < 1) return PT_TEBD_EINVAL;
+  const size_t nn = (size_t)n * n;
+  double2 *da = nullptr, *da0 = nullptr, *drefl = nullptr, *dv = nullptr;
+  double *dw = nullptr, *dtri = nullptr, *dwork = nullptr, *dz = nullptr, *dextra = nullptr;
+  int *dn = nullptr, *dnvec = nullptr, *dstat = nullptr;
+  unsigned long long* dst = nullptr;
+  HeevJob* djob = nullptr;
+  bool ok = hipMalloc(&da, nn * sizeof(double2)) == hipSuccess && hipMalloc(&da0, nn * sizeof(double2)) == hipSuccess &&
+            hipMalloc(&drefl, nn * sizeof(double2)) == hipSuccess && hipMalloc(&dv, nn * sizeof(double2)) == hipSuccess &&
+            hipMalloc(&dw, n * sizeof(double)) == hipSuccess && hipMalloc(&dtri, 6 * n * sizeof(double)) == hipSuccess &&
+            hipMalloc(&dwork, 8 * nn * sizeof(double)) == hipSuccess && hipMalloc(&dz, nn * sizeof(double)) == hipSuccess &&
+            hipMalloc(&dextra, sizeof(double)) == hipSuccess && hipMalloc(&dn, sizeof(int)) == hipSuccess &&
+            hipMalloc(&dnvec, sizeof(int)) == hipSuccess && hipMalloc(&dstat, sizeof(int)) == hipSuccess &&
+            hipMalloc(&dst, 8 * sizeof(unsigned long long)) == hipSuccess && hipMalloc(&djob, sizeof(HeevJob)) == hipSuccess;
+  int rate_khz = 0;
+  ok = ok && hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, 0) == hipSuccess && rate_khz > 0;
+  for (int i = 0; i < 9; ++i) stage_ms[i] = 0.0;
+  if (ok) {
+    HeevJob J{};
+    const int r = rule == 0 ? ptt::RULE_ALL : rule == 1 ? ptt::RULE_EPS : rule == 2 ? ptt::RULE_CAP
+                : rule == 3 ? ptt::RULE_RANK : ptt::RULE_FULL;
+    fill_heev(J, da, n, dn, dw, drefl, dtri, dwork, dz, n, dnvec, r, eps, 0, dextra, eps, dv, n, ptt::SCALE_NONE, dstat);
+    J.stamps = dst;
+    const double zero = 0.0;
+    const int zi = 0;
+    ok = hipMemcpy(da0, a, nn * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dn, &n, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dextra, &zero, sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dstat, &zi, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(djob, &J, sizeof(HeevJob), hipMemcpyHostToDevice) == hipSuccess;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess && hipEventCreate(&e2) == hipSuccess;
+    for (int rep = 0; rep < reps && ok; ++rep) {
+      ok = hipMemcpy(da, da0, nn * sizeof(double2), hipMemcpyDeviceToDevice) == hipSuccess;
+      hipEventRecord(e0, nullptr);
+      ptt::heev_solve_kernel<<<1, ptt::HEEV_SOLVE_THREADS, 0, nullptr>>>(djob, nullptr);
+      hipEventRecord(e1, nullptr);
+      // back-transformation and the two orthonormalisation passes
+      dim3 grid((n + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, 1);
+      ptt::heev_backtransform_kernel<<<grid, ptt::HEEV_THREADS, (size_t)n * ptt::HEEV_BT_COLS * sizeof(double2), nullptr>>>(djob);
+      const int tiles = (n + ptt::GEMM_BM - 1) / ptt::GEMM_BM;
+      for (int pass = 0; pass < 2; ++pass) {
+        ptt::heev_orth_gemm<<<dim3(tiles, tiles, 1), ptt::GEMM_THREADS, 0, nullptr>>>(djob, 0);
+        ptt::heev_orth_mfix<<<dim3(elem_blocks((long long)n * n), 1), kThreads, 0, nullptr>>>(djob);
+        ptt::heev_orth_gemm<<<dim3(tiles, tiles, 1), ptt::GEMM_THREADS, 0, nullptr>>>(djob, 1);
+        ptt::heev_orth_norm<<<dim3((n + 63) / 64, 1), 256, 0, nullptr>>>(djob, 1, pass == 1);
+      }
+      hipEventRecord(e2, nullptr);
+      unsigned long long t[8];
+      float ms_solve = 0.f, ms_rest = 0.f;
+      ok = ok && hipDeviceSynchronize() == hipSuccess &&
+           hipMemcpy(t, dst, 7 * sizeof(unsigned long long), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipEventElapsedTime(&ms_solve, e0, e1) == hipSuccess && hipEventElapsedTime(&ms_rest, e1, e2) == hipSuccess;
+      if (!ok) break;
+      for (int i = 0; i < 6; ++i) stage_ms[i] += (double)(t[i + 1] - t[i]) / rate_khz / reps;
+      stage_ms[6] += ms_solve / reps;
+      stage_ms[7] += ms_rest / reps;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e2) hipEventDestroy(e2);
+  }
+  hipFree(da); hipFree(da0); hipFree(drefl); hipFree(dv); hipFree(dw); hipFree(dtri); hipFree(dwork); hipFree(dz);
+  hipFree(dextra); hipFree(dn); hipFree(dnvec); hipFree(dstat); hipFree(dst); hipFree(djob);
+  return ok ? PT_TEBD_OK : PT_TEBD_EDEVICE;
 }
 
 extern "C" pt_tebd_status pt_test_heev_tridiagonal(int32_t n, const double* a, int32_t rule, double eps, int32_t cap,
