@@ -47,11 +47,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100, help="timed steps from the initial state (the workload has 100)")
     p.add_argument("--warmup", type=int, default=2, help="untimed steps on a throwaway handle per form")
-    p.add_argument("--workload", default="xy21")
+    p.add_argument("--workload", default="xy21", help="xy21, xyz5, xyz3, or batched (many independent chains)")
     p.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_mixed"],
                    help="forms to run; with both, value is the FP32-mixed rate")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="time budget of each oracle CPU baseline run (1 thread, all cores; 0 disables them)")
+    p.add_argument("--chains", type=int, default=256,
+                   help="with --workload batched: number of independent chains in the batch")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="before the workload, run one element-wise copy kernel that reads and writes MIB MiB "
                         "(the reference for hardware byte counters)")
@@ -258,6 +260,83 @@ def cpu_baseline(wl, seconds):
             "sample_1_thread": f"steps 1..{s1}, {t1:.1f} s wall, one BLAS thread"}
 
 
+def run_batched(args):
+    """Many independent chains (the batched workload: chains of 4..16 sites
+    with their own couplings, baths and bond caps) advanced together through
+    one batch: one launch per kernel of a sublayer over every chain's bonds,
+    one time step captured in a HIP graph on the first step (untimed) and
+    replayed for the timed steps."""
+    import torch
+    from paper_2201_05529_amd import binding as B
+    from paper_2201_05529_amd import workloads as W
+    n_chains = args.chains
+    wls = W.batch256(n_chains=n_chains, n_steps=args.steps + 1)
+    horizon = args.steps + 1
+    prec = B.FP32_MIXED if args.precision in ("both", "fp32_mixed") else B.FP64
+    t0 = time.perf_counter()
+    specs = [{"alpha": wl["baths"][0]["alpha"], "wc": wl["baths"][0]["wc"], "temperature": wl["baths"][0]["temperature"],
+              "coupling_op": wl["baths"][0]["coupling_op"], "cutoff": wl["baths"][0]["cutoff"]} for wl in wls]
+    pts = B.build_ptmpo_batch(specs, wls[0]["dt"], horizon, wls[0]["baths"][0]["k_cut"], wls[0]["eps_tempo"],
+                              wls[0]["xi_max"])
+    torch.cuda.synchronize()
+    t_ptmpo = time.perf_counter() - t0
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    chains = []
+    for wl, pt in zip(wls, pts):
+        baths = [{"site": b["site"], "tensors": pt["tensors"]} for b in wl["baths"]]
+        chains.append(B.Chain(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths, chi_max=wl["chi_max"],
+                              xi_max=wl["xi_max"], eps=wl["eps"], precision=prec, stream=stream))
+    batch = B.Batch(chains)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        batch.step(1)   # captures the graph
+    stream.synchronize()
+    t_first = time.perf_counter() - t0
+    for c in chains:
+        c.model_flops(reset=True)
+    site_updates = sum(wl["n_sites"] for wl in wls) * args.steps
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        batch.step(1)
+        stream.synchronize()
+        lat.append(time.perf_counter() - ts)
+        if (k + 1) % 10 == 0:
+            print(f"bench[batched]: step {k + 1}/{args.steps} {time.perf_counter() - t0:.2f} s", file=sys.stderr,
+                  flush=True)
+    elapsed = time.perf_counter() - t0
+    mf = np.sum([c.model_flops() for c in chains], axis=0)
+    traces = []
+    for c, wl in zip(chains, wls):
+        _, tr = c.observe(np.arange(wl["n_sites"], dtype=np.int32), np.array([W.SZ] * wl["n_sites"]))
+        traces.append(tr)
+    batch.close()
+    for c in chains:
+        c.close()
+    lat = np.array(lat) * 1e3
+    form = "fp32_mixed" if prec == B.FP32_MIXED else "fp64"
+    caps = [wl["chi_max"] for wl in wls]
+    out = {
+        "metric": "site-updates/s, batched independent chains (all chains together)",
+        "value": site_updates / elapsed, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64-mfma+f64" if form == "fp32_mixed" else "c128", "data": "synthetic",
+        "config": {"workload": f"batch{n_chains}: {n_chains} XYZ chains, N~U{{4..16}} ({sum(w['n_sites'] for w in wls)} "
+                               f"sites), chi cap in {{16,32,64}} ({caps.count(16)}/{caps.count(32)}/{caps.count(64)}), "
+                               f"xi<=24, K=20, dt=0.05, a bath on every site; timed steps 2..{args.steps + 1} "
+                               f"(step 1 captures the HIP graph, {t_first:.2f} s)",
+                   "form": form, "ptmpo_build_s": t_ptmpo, "ptmpo_builds": n_chains, "create_s": t_create,
+                   "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                   "trace_range": [float(np.min(np.real(traces))), float(np.max(np.real(traces)))],
+                   "composite_roofline": composite_roofline(mf, elapsed, form)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -280,6 +359,9 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "batched":
+        run_batched(args)
+        return
     wl = getattr(W, args.workload)()
     n = wl["n_sites"]
     horizon = max(args.steps, args.warmup, wl["n_steps"])
