@@ -237,8 +237,10 @@ void pt_mpo_free(pt_tebd_bath* bath);
  * the GPU: every bath is one work item of the batched window sweeps (right
  * to left LQ factorisations, left to right truncated SVDs through Gram
  * matrices and the double-precision eigensolver).  params[b] gives alpha,
- * wc, temperature, cutoff_kind and the coupling operator of bath b; dt,
- * n_steps, mem_steps, eps and xi_max (<= 256) are shared.  out[b] is filled
+ * wc, temperature, cutoff_kind, the coupling operator and the length of
+ * bath b's PT-MPO (a build of M steps equals the single build of M steps:
+ * builds advance in lockstep and one of them stops at its own length); dt,
+ * mem_steps, eps and xi_max (<= 256) are shared, n_steps is the longest.  out[b] is filled
  * as by pt_mpo_build_ohmic (library-owned host arrays, free each with
  * pt_mpo_free).  Device memory (about (mem_steps + 6) (4 xi_max)^2 * 64 B
  * plus n_steps xi_max^2 * 64 B per bath) is allocated and freed by the call;
@@ -247,6 +249,7 @@ typedef struct {
   double alpha, wc, temperature;
   int32_t cutoff_kind;
   const double* coupling_op;   /* d x d Hermitian, complex */
+  int32_t n_steps;             /* this bath's PT-MPO length, 1..n_steps of the call; 0: the call's n_steps */
 } pt_bath_params;
 pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_bath_params* params, double dt,
                                         int32_t n_steps, int32_t mem_steps, double eps, int32_t xi_max,

@@ -33,7 +33,8 @@ class Bath(ctypes.Structure):
 
 class BathParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("wc", ctypes.c_double), ("temperature", ctypes.c_double),
-                ("cutoff_kind", ctypes.c_int32), ("coupling_op", ctypes.POINTER(ctypes.c_double))]
+                ("cutoff_kind", ctypes.c_int32), ("coupling_op", ctypes.POINTER(ctypes.c_double)),
+                ("n_steps", ctypes.c_int32)]
 
 
 class Config(ctypes.Structure):
@@ -156,7 +157,9 @@ def _bath_to_dict(b, n_steps):
 
 def build_ptmpo_batch(baths, dt, n_steps, mem_steps, eps, xi_max, stream=None):
     """PT-MPOs of many baths at once on the GPU (pt_mpo_build_ohmic_batch).
-    `baths`: list of dict(alpha, wc, temperature, coupling_op, cutoff='exp')."""
+    `baths`: list of dict(alpha, wc, temperature, coupling_op, cutoff='exp',
+    n_steps=None); a bath's own n_steps (at most the call's) sets the length
+    of its PT-MPO."""
     import torch
     n = len(baths)
     ops = [_cplx(b["coupling_op"]) for b in baths]
@@ -165,6 +168,7 @@ def build_ptmpo_batch(baths, dt, n_steps, mem_steps, eps, xi_max, stream=None):
         params[i].alpha, params[i].wc, params[i].temperature = b["alpha"], b["wc"], b["temperature"]
         params[i].cutoff_kind = 0 if b.get("cutoff", "exp") == "exp" else 1
         params[i].coupling_op = _dptr(ops[i])
+        params[i].n_steps = int(b.get("n_steps") or 0)
     outs = (Bath * n)()
     s = stream if stream is not None else torch.cuda.current_stream()
     st = lib().pt_mpo_build_ohmic_batch(n, params, float(dt), int(n_steps), int(mem_steps), float(eps), int(xi_max),
@@ -174,10 +178,79 @@ def build_ptmpo_batch(baths, dt, n_steps, mem_steps, eps, xi_max, stream=None):
     res = []
     for i in range(n):
         try:
-            res.append(_bath_to_dict(outs[i], n_steps))
+            res.append(_bath_to_dict(outs[i], int(baths[i].get("n_steps") or n_steps)))
         finally:
             lib().pt_mpo_free(ctypes.byref(outs[i]))
     return res
+
+
+def _make_config(h_site, h_bond, rho0, dt, baths=(), chi_max=64, xi_max=None, eps=1e-7, precision=FP64,
+                 lindblad=None, seed=220105529):
+    """Marshal a chain description into a pt_tebd_config; returns it with
+    the host arrays it points to (kept alive by the caller)."""
+    n_sites = len(h_site)
+    keep = []
+    hs = _cplx(h_site)
+    hb = _cplx(h_bond) if n_sites > 1 else np.zeros(2)
+    r0 = _cplx(rho0)
+    keep += [hs, hb, r0]
+    cfg = Config()
+    cfg.n_sites, cfg.d, cfg.dt = n_sites, 2, float(dt)
+    cfg.h_site, cfg.h_bond, cfg.rho0 = _dptr(hs), _dptr(hb), _dptr(r0)
+    if lindblad is not None:
+        # the ABI takes the same number of GKSL operators per site: pad
+        # ragged per-site lists with zero operators
+        n_l = max(len(ops) for ops in lindblad)
+        full = np.zeros((n_sites, max(n_l, 1), 2, 2), dtype=np.complex128)
+        for s_, ops in enumerate(lindblad):
+            for k_, op in enumerate(ops):
+                full[s_, k_] = op
+        ld = _cplx(full)
+        keep.append(ld)
+        cfg.n_lindblad, cfg.lindblad = n_l, _dptr(ld)
+    else:
+        cfg.n_lindblad, cfg.lindblad = 0, None
+    bath_structs = (Bath * max(len(baths), 1))()
+    xi_needed = 1
+    for i, b in enumerate(baths):
+        tens = [np.asarray(t, dtype=np.complex128) for t in b["tensors"]]
+        m = len(tens)
+        dims = np.array([tens[0].shape[0]] + [t.shape[1] for t in tens], dtype=np.int32)
+        xi_needed = max(xi_needed, int(dims.max()))
+        flats = [_cplx(t) for t in tens]
+        tptr = (ctypes.POINTER(ctypes.c_double) * m)(*[_dptr(f) for f in flats])
+        keep += [dims, flats, tptr]
+        bs = bath_structs[i]
+        bs.site, bs.n_steps, bs.diagonal = int(b["site"]), m, 1 if tens[0].ndim == 3 else 0
+        bs.bond_dims = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        bs.tensors = tptr
+        if b.get("caps") is not None:
+            cflats = [_cplx(c) for c in b["caps"]]
+            cptr = (ctypes.POINTER(ctypes.c_double) * (m + 1))(*[_dptr(f) for f in cflats])
+            keep += [cflats, cptr]
+            bs.caps = cptr
+        else:
+            bs.caps = None
+    keep.append(bath_structs)
+    cfg.n_baths = len(baths)
+    cfg.baths = bath_structs
+    cfg.chi_max = int(chi_max)
+    cfg.xi_max = int(xi_max if xi_max is not None else xi_needed)
+    cfg.svd_rel_cutoff = float(eps)
+    cfg.precision = int(precision)
+    cfg.seed = int(seed)
+    return cfg, keep
+
+
+def workspace_bytes(h_site, h_bond, rho0, dt, baths=(), chi_max=64, xi_max=None, eps=1e-7, precision=FP64,
+                    lindblad=None):
+    """Device bytes a handle for this chain needs (pt_tebd_workspace_size)."""
+    cfg, keep = _make_config(h_site, h_bond, rho0, dt, baths, chi_max, xi_max, eps, precision, lindblad)
+    size = ctypes.c_size_t()
+    st = lib().pt_tebd_workspace_size(ctypes.byref(cfg), ctypes.byref(size))
+    if st != 0:
+        raise PtTebdError(st, "pt_tebd_workspace_size")
+    return size.value
 
 
 class Chain:
@@ -192,57 +265,9 @@ class Chain:
             raise RuntimeError("pt_tebd needs a GPU")
         self._torch = torch
         L = lib()
-        n_sites = len(h_site)
-        self._keep = []
-        hs = _cplx(h_site)
-        hb = _cplx(h_bond) if n_sites > 1 else np.zeros(2)
-        r0 = _cplx(rho0)
-        self._keep += [hs, hb, r0]
-        cfg = Config()
-        cfg.n_sites, cfg.d, cfg.dt = n_sites, 2, float(dt)
-        cfg.h_site, cfg.h_bond, cfg.rho0 = _dptr(hs), _dptr(hb), _dptr(r0)
-        if lindblad is not None:
-            # the ABI takes the same number of GKSL operators per site: pad
-            # ragged per-site lists with zero operators
-            n_l = max(len(ops) for ops in lindblad)
-            full = np.zeros((n_sites, max(n_l, 1), 2, 2), dtype=np.complex128)
-            for s_, ops in enumerate(lindblad):
-                for k_, op in enumerate(ops):
-                    full[s_, k_] = op
-            ld = _cplx(full)
-            self._keep.append(ld)
-            cfg.n_lindblad, cfg.lindblad = n_l, _dptr(ld)
-        else:
-            cfg.n_lindblad, cfg.lindblad = 0, None
-        bath_structs = (Bath * max(len(baths), 1))()
-        xi_needed = 1
-        for i, b in enumerate(baths):
-            tens = [np.asarray(t, dtype=np.complex128) for t in b["tensors"]]
-            m = len(tens)
-            dims = np.array([tens[0].shape[0]] + [t.shape[1] for t in tens], dtype=np.int32)
-            xi_needed = max(xi_needed, int(dims.max()))
-            flats = [_cplx(t) for t in tens]
-            tptr = (ctypes.POINTER(ctypes.c_double) * m)(*[_dptr(f) for f in flats])
-            self._keep += [dims, flats, tptr]
-            bs = bath_structs[i]
-            bs.site, bs.n_steps, bs.diagonal = int(b["site"]), m, 1 if tens[0].ndim == 3 else 0
-            bs.bond_dims = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-            bs.tensors = tptr
-            if b.get("caps") is not None:
-                cflats = [_cplx(c) for c in b["caps"]]
-                cptr = (ctypes.POINTER(ctypes.c_double) * (m + 1))(*[_dptr(f) for f in cflats])
-                self._keep += [cflats, cptr]
-                bs.caps = cptr
-            else:
-                bs.caps = None
-        self._keep.append(bath_structs)
-        cfg.n_baths = len(baths)
-        cfg.baths = bath_structs
-        cfg.chi_max = int(chi_max)
-        cfg.xi_max = int(xi_max if xi_max is not None else xi_needed)
-        cfg.svd_rel_cutoff = float(eps)
-        cfg.precision = int(precision)
-        cfg.seed = int(seed)
+        cfg, self._keep = _make_config(h_site, h_bond, rho0, dt, baths, chi_max, xi_max, eps, precision, lindblad,
+                                       seed)
+        n_sites = cfg.n_sites
         self.n_sites = n_sites
         size = ctypes.c_size_t()
         st = L.pt_tebd_workspace_size(ctypes.byref(cfg), ctypes.byref(size))

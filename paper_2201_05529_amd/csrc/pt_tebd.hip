@@ -1760,9 +1760,11 @@ extern "C" pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_ba
   std::vector<std::vector<cplx>> us(n_builds);
   std::vector<char> diag(n_builds);
   std::vector<double2> bfac((size_t)n_builds * (K + 1) * 16);
+  std::vector<int> len(n_builds);
   for (int b = 0; b < n_builds; ++b) {
     const pt_bath_params& P = params[b];
-    if (!P.coupling_op) return PT_TEBD_EINVAL;
+    if (!P.coupling_op || P.n_steps < 0 || P.n_steps > n_steps) return PT_TEBD_EINVAL;
+    len[b] = P.n_steps > 0 ? P.n_steps : n_steps;
     bool dg = false;
     if (!coupling_basis(P.coupling_op, sigmas[b], us[b], dg)) return PT_TEBD_EINVAL;
     diag[b] = dg;
@@ -1805,7 +1807,7 @@ extern "C" pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_ba
     dv.rlr = bp.take<ptt::RefineJob>(n_builds);
     for (int b = 0; b < n_builds; ++b) {
       ptt::TempoJob J{};
-      J.K = K; J.M = M; J.xi_cap = xi_max; J.acap = acap; J.eps = eps;
+      J.K = K; J.M = len[b]; J.xi_cap = xi_max; J.acap = acap; J.eps = eps;
       J.bfac = dv.bf ? dv.bf + (size_t)b * (K + 1) * 16 : nullptr;
       J.slots = bp.take<double2>((size_t)(K + 1) * slot);
       J.sa = bp.take<int>(K + 1);
@@ -1920,16 +1922,17 @@ extern "C" pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_ba
   ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
   // results to the host
   for (int b = 0; b < n_builds && ok; ++b) {
-    std::vector<int> dims(M + 1);
+    const int Mb = len[b];
+    std::vector<int> dims(Mb + 1);
     int status = 0;
-    std::vector<double2> o((size_t)M * xi_max * xi_max * 4);
-    ok = hipMemcpy(dims.data(), jobs[b].out_dims, (M + 1) * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+    std::vector<double2> o((size_t)Mb * xi_max * xi_max * 4);
+    ok = hipMemcpy(dims.data(), jobs[b].out_dims, (Mb + 1) * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
          hipMemcpy(&status, jobs[b].status, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
          hipMemcpy(o.data(), jobs[b].out, o.size() * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess;
     if (!ok) break;
     if (status & 4) { ok = false; break; }
-    std::vector<std::vector<cplx>> tens(M);
-    for (int k = 0; k < M; ++k) {
+    std::vector<std::vector<cplx>> tens(Mb);
+    for (int k = 0; k < Mb; ++k) {
       const int xa = dims[k], xb = dims[k + 1];
       tens[k].resize((size_t)xa * xb * 4);
       for (size_t q = 0; q < tens[k].size(); ++q) {
@@ -1937,7 +1940,7 @@ extern "C" pt_tebd_status pt_mpo_build_ohmic_batch(int32_t n_builds, const pt_ba
         tens[k][q] = {v.x, v.y};
       }
     }
-    fill_bath(M, dims, tens, diag[b] != 0, us[b], &out[b]);
+    fill_bath(Mb, dims, tens, diag[b] != 0, us[b], &out[b]);
   }
   (void)hipFree(ws);
   return ok ? PT_TEBD_OK : PT_TEBD_EDEVICE;

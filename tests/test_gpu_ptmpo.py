@@ -110,3 +110,19 @@ def test_chain_with_gpu_ptmpo_matches_oracle():
         err = max(err, np.abs(v - np.array([eng.expectation(s, W.SZ) for s in range(3)])).max())
     print(f"xyz3 with the GPU PT-MPO: max |d<sz>| {err:.1e}", flush=True)
     assert err < 1e-5
+
+
+def test_builds_of_different_lengths_in_one_call_equal_single_builds():
+    # a bath's own length: builds advance in lockstep and each stops at its
+    # own length, so every build equals the build made alone
+    from paper_2201_05529_amd import binding as B
+    specs = [{"alpha": 0.1, "wc": 4.0, "temperature": 1.2, "coupling_op": W.SZ, "n_steps": 7},
+             {"alpha": 0.2, "wc": 4.0, "temperature": 0.8, "coupling_op": W.SZ, "n_steps": 12},
+             {"alpha": 0.15, "wc": 4.0, "temperature": 2.0, "coupling_op": W.SZ, "n_steps": 3}]
+    together = B.build_ptmpo_batch(specs, 0.1, 12, 4, 1e-9, 32)
+    for spec, pt in zip(specs, together):
+        alone = B.build_ptmpo_batch([dict(spec, n_steps=None)], 0.1, spec["n_steps"], 4, 1e-9, 32)[0]
+        assert len(pt["tensors"]) == spec["n_steps"]
+        assert pt["bond_dims"] == alone["bond_dims"]
+        for a, b in zip(pt["tensors"], alone["tensors"]):
+            assert np.array_equal(a, b)
