@@ -47,13 +47,16 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100, help="timed steps from the initial state (the workload has 100)")
     p.add_argument("--warmup", type=int, default=2, help="untimed steps on a throwaway handle per form")
-    p.add_argument("--workload", default="xy21", help="xy21, xyz5, xyz3, or batched (many independent chains)")
+    p.add_argument("--workload", default="xy21", help="xy21, xyz5, xyz3, batched (many independent chains) or serving (the request stream)")
     p.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_mixed"],
                    help="forms to run; with both, value is the FP32-mixed rate")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="time budget of each oracle CPU baseline run (1 thread, all cores; 0 disables them)")
     p.add_argument("--chains", type=int, default=256,
                    help="with --workload batched: number of independent chains in the batch")
+    p.add_argument("--requests", type=int, default=24, help="with --workload serving: requests taken from the stream")
+    p.add_argument("--steps-scale", type=float, default=0.1,
+                   help="with --workload serving: factor on each request's step count")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="before the workload, run one element-wise copy kernel that reads and writes MIB MiB "
                         "(the reference for hardware byte counters)")
@@ -337,6 +340,60 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serving(args):
+    """The request stream of the serving workload (Poisson arrivals at
+    50 requests/s; N ~ U{3..32}, chi cap in {16, 32, 64, 128}, xi <= 32,
+    dt = 0.05, K = 20, a bath on every site) through the continuous-batching
+    loop: the first --requests requests, each request's step count scaled by
+    --steps-scale (the full stream offers far more work than one GPU
+    sustains: about 3,900 site-updates per request at 50 requests/s)."""
+    import torch
+    from paper_2201_05529_amd import binding as B
+    from paper_2201_05529_amd import serving as S
+    from paper_2201_05529_amd import workloads as W
+    reqs = W.serving_stream()[: args.requests]
+    full_steps = [wl["n_steps"] for wl in reqs]
+    for wl in reqs:
+        wl["n_steps"] = max(1, int(round(wl["n_steps"] * args.steps_scale)))
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    prec = B.FP32_MIXED if args.precision in ("both", "fp32_mixed") else B.FP64
+    srv = S.Server(budget, precision=prec, max_active=256, max_admit=64)
+
+    def log(msg):
+        print("bench[serving]: " + msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True, log=log)
+    wall = time.perf_counter() - t0
+    lat = np.array([r.latency for r in res])
+    wait = np.array([r.admitted - r.arrival for r in res])
+    su = sum(r.site_updates for r in res)
+    offered = sum(wl["n_sites"] * wl["n_steps"] for wl in reqs) / max(reqs[-1]["arrival_s"], 1e-9)
+    caps = [wl["chi_max"] for wl in reqs]
+    form = "fp32_mixed" if prec == B.FP32_MIXED else "fp64"
+    out = {
+        "metric": "serving: p50/p99 request latency and site-updates/s under continuous batching",
+        "value": su / wall, "unit": "site-updates/s", "n_gpus": 1, "steps": int(sum(wl["n_steps"] for wl in reqs)),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64-mfma+f64" if form == "fp32_mixed" else "c128", "data": "synthetic",
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "config": {"workload": f"serving: first {len(reqs)} requests of the Poisson stream (50/s), N~U{{3..32}}, "
+                               f"chi cap in {{16,32,64,128}} ({caps.count(16)}/{caps.count(32)}/{caps.count(64)}/"
+                               f"{caps.count(128)}), xi<=32, K=20, dt=0.05, steps U{{50..400}} scaled by "
+                               f"{args.steps_scale} (mean {np.mean([wl['n_steps'] for wl in reqs]):.1f}, "
+                               f"unscaled mean {np.mean(full_steps):.1f})",
+                   "form": form, "budget_bytes": budget, "wall_s": wall, "site_updates": su,
+                   "offered_site_updates_per_s": offered,
+                   "latency_s": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                                 "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+                   "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+                   "latency_definition": "completion (final observables on the host) minus arrival; includes "
+                                         "queueing, the PT-MPO build and every step"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -361,6 +418,9 @@ def main():
         del src, dst
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
     wl = getattr(W, args.workload)()
     n = wl["n_sites"]
