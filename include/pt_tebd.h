@@ -138,6 +138,40 @@ pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a
                                  int32_t site_b, const double* op_b, int32_t n_steps,
                                  double* out);
 
+/* Multi-time correlation (Appendix A.4, eq. two-time-corr-decomposed with P
+ * insertions): from the current step t a device copy X of the augmented
+ * state is propagated; at step offset offsets[p] (non-decreasing, >= 0) the
+ * super-operator of ops[p] (complex 2x2, row-major) acts on site sites[p],
+ * from the left (sides[p] = 0: C rho, the C^L of the paper) or from the
+ * right (sides[p] = 1: rho C, the C^R of out-of-time-ordered correlations).
+ * out[j] = Tr[B X(t + (m_P + j) dt)] / Tr rho(t), j = 0..n_steps, m_P the
+ * last offset (complex, interleaved).  pt_tebd_correlate is the case of one
+ * left insertion at offset 0.  The handle's own state is not changed.
+ * EINVAL for offsets out of order, sides other than 0 or 1, sites out of
+ * range or non-finite operators; ERANGE when the propagation runs past a
+ * PT-MPO.  Syncs. */
+pt_tebd_status pt_tebd_correlate_multi(pt_tebd_t h, int32_t n_ins, const int32_t* offsets, const int32_t* sites,
+                                       const double* ops, const int32_t* sides, int32_t site_b, const double* op_b,
+                                       int32_t n_steps, double* out);
+
+/* Fluctuation and dissipation spectra of a Hermitian single-site operator A
+ * at the current (steady) state, Sec. III.A and Appendix B.2: the
+ * auto-correlation C(tau_j) = <A(tau_j) A(0)> = Tr[A X(t + tau_j)] / Tr rho(t)
+ * with X(t) = A rho(t), tau_j = j dt, j = 0..n_steps, goes to corr (complex,
+ * interleaved, n_steps + 1 values).  Continued to negative times by
+ * C(-tau) = C(tau)^* and transformed on [-n_steps dt, n_steps dt] with the
+ * trapezoid rule at the n_omega angular frequencies omega:
+ *   s_out[k]   = S_A(w)   = dt sum_j c_j Re C(tau_j) cos(w tau_j)
+ *   chi_out[k] = chi''_A(w) = -dt sum_j c_j Im C(tau_j) sin(w tau_j)
+ * with c_0 = c_n = 1 and c_j = 2 otherwise, so S_A is the transform of
+ * 1/2 <{A(tau), A(0)}> and chi''_A the imaginary part of the transform of
+ * i Theta(tau) <[A(tau), A(0)]>.  For a thermal state at temperature T,
+ * S_A / chi''_A = coth(w / 2T).  The transform runs on the device (one
+ * thread per frequency); the call allocates and frees small device buffers
+ * and syncs.  EINVAL for a non-Hermitian A. */
+pt_tebd_status pt_tebd_fdt_spectra(pt_tebd_t h, int32_t site, const double* op, int32_t n_steps, int32_t n_omega,
+                                   const double* omega, double* corr, double* s_out, double* chi_out);
+
 /* Current chain bond dimensions chi[N-1] and augmented dims xi[N] (xi may be
  * NULL).  Syncs. */
 pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi);

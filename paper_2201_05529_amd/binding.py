@@ -70,6 +70,8 @@ def lib():
         L.pt_tebd_correlate.argtypes = [vp, i32, dp, i32, dp, i32, dp]
         L.pt_tebd_bond_dims.argtypes = [vp, ip, ip]
         L.pt_tebd_model_flops.argtypes = [vp, dp, i32]
+        L.pt_tebd_correlate_multi.argtypes = [vp, i32, ip, ip, dp, ip, i32, dp, i32, dp]
+        L.pt_tebd_fdt_spectra.argtypes = [vp, i32, dp, i32, i32, dp, dp, dp, dp]
         L.pt_tebd_snapshot.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
         L.pt_tebd_restore.argtypes = [vp, vp, ctypes.c_size_t]
         L.pt_tebd_current_step.argtypes = [vp]
@@ -314,6 +316,34 @@ class Chain:
         self._check(lib().pt_tebd_bond_dims(self.handle, chi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                             xi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "bond_dims")
         return chi[:self.n_sites - 1].copy(), xi
+
+    def correlate_multi(self, insertions, site_b, op_b, n_steps):
+        """insertions: list of (offset, site, op 2x2, side "L" or "R");
+        returns the complex array out[0..n_steps] (pt_tebd_correlate_multi)."""
+        n = len(insertions)
+        offs = np.array([int(m) for m, _, _, _ in insertions], dtype=np.int32)
+        sites = np.array([int(s_) for _, s_, _, _ in insertions], dtype=np.int32)
+        sides = np.array([0 if side == "L" else 1 for _, _, _, side in insertions], dtype=np.int32)
+        ops = _cplx(np.array([op for _, _, op, _ in insertions]))
+        ob = _cplx(op_b)
+        out = np.zeros(2 * (n_steps + 1))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self._check(lib().pt_tebd_correlate_multi(self.handle, n, offs.ctypes.data_as(ip), sites.ctypes.data_as(ip),
+                                                  _dptr(ops), sides.ctypes.data_as(ip), int(site_b), _dptr(ob),
+                                                  int(n_steps), _dptr(out)), "correlate_multi")
+        return out.view(np.complex128)
+
+    def fdt_spectra(self, site, op, n_steps, omega):
+        """(corr, S(omega), chi''(omega)) of a Hermitian single-site operator
+        at the current state (pt_tebd_fdt_spectra)."""
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        corr = np.zeros(2 * (n_steps + 1))
+        s_ = np.zeros(len(om))
+        chi = np.zeros(len(om))
+        opc = _cplx(op)
+        self._check(lib().pt_tebd_fdt_spectra(self.handle, int(site), _dptr(opc), int(n_steps), len(om),
+                                              _dptr(om), _dptr(corr), _dptr(s_), _dptr(chi)), "fdt_spectra")
+        return corr.view(np.complex128), s_, chi
 
     def model_flops(self, reset=False):
         """Minimal algorithmic flops F_a1..F_a4 of the bond updates so far

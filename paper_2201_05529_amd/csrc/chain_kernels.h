@@ -281,4 +281,32 @@ __global__ void k_obs_ops(const ChainDev* chain, ObsScratch S, const int* sites,
   }
 }
 
+// Fluctuation and dissipation spectra (Sec. III.A) of a stationary
+// auto-correlation C(tau_j) = <A(tau_j) A(0)>, tau_j = j dt, j = 0..n, of a
+// Hermitian A, continued to negative times by C(-tau) = C(tau)^*.  With the
+// trapezoid rule on [-n dt, n dt]:
+//   S(w)   = dt sum_j c_j Re C(tau_j) cos(w tau_j)      (Fourier transform of 1/2 <{A(tau), A}>)
+//   chi(w) = -dt sum_j c_j Im C(tau_j) sin(w tau_j)      (imaginary part of the transformed
+//                                                         i Theta(tau) <[A(tau), A]>)
+// where the sums run over j = 0..n, c_0 = 1, c_j = 2 for 0 < j < n, c_n = 1
+// (the two halves of the symmetric interval folded onto j >= 0).  One
+// thread per frequency; the sum over j in a fixed order.
+__global__ void k_fdt_spectra(const double2* corr, int n, double dt, const double* omega, int n_omega, double* s_out,
+                              double* chi_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_omega) return;
+  const double w = omega[k];
+  double s = 0.0, c = 0.0;
+  for (int j = 0; j <= n; ++j) {
+    const double cj = (j == 0 || j == n) ? 1.0 : 2.0;
+    double sn, cs;
+    sincos(w * j * dt, &sn, &cs);
+    s += cj * corr[j].x * cs;
+    c -= cj * corr[j].y * sn;
+  }
+  if (n == 0) c = 0.0;
+  s_out[k] = dt * s;
+  chi_out[k] = dt * c;
+}
+
 }  // namespace ptt

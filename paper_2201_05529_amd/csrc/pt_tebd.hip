@@ -1069,18 +1069,56 @@ pt_tebd_status pt_tebd_observe(pt_tebd_t h, int32_t n_ops, const int32_t* sites,
   return PT_TEBD_OK;
 }
 
-pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a, int32_t site_b,
-                                 const double* op_b, int32_t n_steps, double* out) {
-  if (!h || !op_a || !op_b || !out || n_steps < 0) return PT_TEBD_EINVAL;
-  if (site_a < 0 || site_a >= h->n_sites || site_b < 0 || site_b >= h->n_sites) return PT_TEBD_EINVAL;
+namespace {
+// one insertion of a multi-time correlation: at step offset m the
+// super-operator of op acts on site from the left (side 0: C rho) or from
+// the right (side 1: rho C)
+struct Insertion {
+  int m, site, side;
+  const double* op;
+};
+
+// site super-operator in the site-major vec convention (row index i*2+j of
+// rho_ij): left  (C rho)_ij = sum_k C_ik rho_kj,  right (rho C)_ij = sum_l rho_il C_lj
+void site_superop(const double* op, int side, std::vector<double2>& sop) {
+  sop.assign(16, ptt::mk<double>(0.0, 0.0));
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k)
+        for (int l = 0; l < 2; ++l) {
+          double re = 0, im = 0;
+          if (side == 0 && j == l) { re = op[2 * (i * 2 + k)]; im = op[2 * (i * 2 + k) + 1]; }
+          if (side == 1 && i == k) { re = op[2 * (l * 2 + j)]; im = op[2 * (l * 2 + j) + 1]; }
+          sop[(i * 2 + j) * 4 + (k * 2 + l)] = ptt::mk<double>(re, im);
+        }
+}
+
+// Appendix A.4, eq. two-time-corr-decomposed generalised to P insertions:
+// fork the augmented state at the current step, apply the insertions at
+// their offsets (stepping the fork in between), then read Tr[B X] at offsets
+// m_P + j, j = 0..n_steps, divided by Tr rho at the fork step.
+pt_tebd_status correlate_impl(pt_tebd* h, const std::vector<Insertion>& ins, int32_t site_b, const double* op_b,
+                              int32_t n_steps, double* out) {
+  if (!op_b || !out || n_steps < 0 || ins.empty()) return PT_TEBD_EINVAL;
+  if (site_b < 0 || site_b >= h->n_sites) return PT_TEBD_EINVAL;
+  int last = 0;
+  for (const Insertion& p : ins) {
+    if (!p.op || p.site < 0 || p.site >= h->n_sites || p.m < last || (p.side != 0 && p.side != 1)) {
+      h->err = "insertions need sites in range, sides 0 or 1 and non-decreasing offsets from 0";
+      return PT_TEBD_EINVAL;
+    }
+    last = p.m;
+    for (int i = 0; i < 8; ++i)
+      if (!std::isfinite(p.op[i])) { h->err = "non-finite operator"; return PT_TEBD_EINVAL; }
+  }
   for (int i = 0; i < 8; ++i)
-    if (!std::isfinite(op_a[i]) || !std::isfinite(op_b[i])) { h->err = "non-finite operator"; return PT_TEBD_EINVAL; }
-  if (h->n_baths > 0 && h->step + n_steps > h->pt_steps) {
+    if (!std::isfinite(op_b[i])) { h->err = "non-finite operator"; return PT_TEBD_EINVAL; }
+  if (h->n_baths > 0 && h->step + last + n_steps > h->pt_steps) {
     h->err = "correlation runs past the end of a PT-MPO";
     return PT_TEBD_ERANGE;
   }
   TimingScope timing(h);
-  // trace of the main state at the insertion time
+  // trace of the main state at the fork step
   const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
   double ov[8];
   obs_vector(eye, ov);
@@ -1104,31 +1142,75 @@ pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a
             check(hipMemcpyAsync(F.log_scale, M.log_scale, sizeof(double), hipMemcpyDeviceToDevice, h->stream), h, "fork") &&
             check(hipMemsetAsync(F.status, 0, sizeof(int), h->stream), h, "fork");
   if (!ok) return PT_TEBD_EDEVICE;
-  // A acting from the left: (A kron 1) in the site Liouville space
-  std::vector<double2> sop(16);
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int k = 0; k < 2; ++k)
-        for (int l = 0; l < 2; ++l) {
-          double re = 0, im = 0;
-          if (j == l) { re = op_a[2 * (i * 2 + k)]; im = op_a[2 * (i * 2 + k) + 1]; }
-          sop[(i * 2 + j) * 4 + (k * 2 + l)] = ptt::mk<double>(re, im);
-        }
-  if (!check(hipMemcpyAsync(h->site_op, sop.data(), 16 * sizeof(double2), hipMemcpyHostToDevice, h->stream), h, "op"))
-    return PT_TEBD_EDEVICE;
-  ptt::k_apply_site_op<<<elem_blocks((long long)c.chi_cap * c.xi_cap * c.chi_cap), kThreads, 0, h->stream>>>(
-      h->chains + 1, site_a, h->site_op);
+  int offset = 0;
+  std::vector<double2> sop;
+  for (const Insertion& p : ins) {
+    for (int k = offset; k < p.m; ++k) step_chain(h, 1, h->step + k + 1);
+    offset = p.m;
+    site_superop(p.op, p.side, sop);
+    if (!check(hipMemcpyAsync(h->site_op, sop.data(), 16 * sizeof(double2), hipMemcpyHostToDevice, h->stream), h, "op") ||
+        !check(hipStreamSynchronize(h->stream), h, "op sync"))
+      return PT_TEBD_EDEVICE;
+    ptt::k_apply_site_op<<<elem_blocks((long long)c.chi_cap * c.xi_cap * c.chi_cap), kThreads, 0, h->stream>>>(
+        h->chains + 1, p.site, h->site_op);
+  }
   double obv[8];
   obs_vector(op_b, obv);
   for (int j = 0; j <= n_steps; ++j) {
-    if (j > 0) step_chain(h, 1, h->step + j);
-    s = observe_raw(h, 1, h->step + j, 1, &site_b, obv, num, den, lg);
+    if (j > 0) step_chain(h, 1, h->step + offset + j);
+    s = observe_raw(h, 1, h->step + offset + j, 1, &site_b, obv, num, den, lg);
     if (s != PT_TEBD_OK) return s;
     const std::complex<double> v = num[0] * std::exp(lg[0] - tr0_log) / tr0;
     out[2 * j] = v.real();
     out[2 * j + 1] = v.imag();
   }
   return PT_TEBD_OK;
+}
+}  // namespace
+
+pt_tebd_status pt_tebd_correlate(pt_tebd_t h, int32_t site_a, const double* op_a, int32_t site_b,
+                                 const double* op_b, int32_t n_steps, double* out) {
+  if (!h || !op_a) return PT_TEBD_EINVAL;
+  return correlate_impl(h, {Insertion{0, site_a, 0, op_a}}, site_b, op_b, n_steps, out);
+}
+
+pt_tebd_status pt_tebd_fdt_spectra(pt_tebd_t h, int32_t site, const double* op, int32_t n_steps, int32_t n_omega,
+                                   const double* omega, double* corr, double* s_out, double* chi_out) {
+  if (!h || !op || !omega || !corr || !s_out || !chi_out || n_omega < 1 || n_steps < 0) return PT_TEBD_EINVAL;
+  for (int i = 0; i < 4; ++i)  // Hermitian: op = op^H
+    if (std::fabs(op[2 * i] - op[2 * ((i % 2) * 2 + i / 2)]) > 1e-12 * (1.0 + std::fabs(op[2 * i])) ||
+        std::fabs(op[2 * i + 1] + op[2 * ((i % 2) * 2 + i / 2) + 1]) > 1e-12 * (1.0 + std::fabs(op[2 * i + 1]))) {
+      h->err = "the spectra need a Hermitian operator";
+      return PT_TEBD_EINVAL;
+    }
+  pt_tebd_status s = correlate_impl(h, {Insertion{0, site, 0, op}}, site, op, n_steps, corr);
+  if (s != PT_TEBD_OK) return s;
+  double2* dc = nullptr;
+  double *dw = nullptr, *ds = nullptr, *dx = nullptr;
+  bool ok = check(hipMalloc(&dc, (n_steps + 1) * sizeof(double2)), h, "spectra") &&
+            check(hipMalloc(&dw, n_omega * sizeof(double)), h, "spectra") &&
+            check(hipMalloc(&ds, n_omega * sizeof(double)), h, "spectra") &&
+            check(hipMalloc(&dx, n_omega * sizeof(double)), h, "spectra") &&
+            check(hipMemcpyAsync(dc, corr, (n_steps + 1) * sizeof(double2), hipMemcpyHostToDevice, h->stream), h, "spectra") &&
+            check(hipMemcpyAsync(dw, omega, n_omega * sizeof(double), hipMemcpyHostToDevice, h->stream), h, "spectra");
+  if (ok) {
+    ptt::k_fdt_spectra<<<(n_omega + 255) / 256, 256, 0, h->stream>>>(dc, n_steps, h->dt, dw, n_omega, ds, dx);
+    ok = check(hipGetLastError(), h, "spectra") &&
+         check(hipMemcpyAsync(s_out, ds, n_omega * sizeof(double), hipMemcpyDeviceToHost, h->stream), h, "spectra") &&
+         check(hipMemcpyAsync(chi_out, dx, n_omega * sizeof(double), hipMemcpyDeviceToHost, h->stream), h, "spectra") &&
+         check(hipStreamSynchronize(h->stream), h, "spectra");
+  }
+  (void)hipFree(dc); (void)hipFree(dw); (void)hipFree(ds); (void)hipFree(dx);
+  return ok ? PT_TEBD_OK : PT_TEBD_EDEVICE;
+}
+
+pt_tebd_status pt_tebd_correlate_multi(pt_tebd_t h, int32_t n_ins, const int32_t* offsets, const int32_t* sites,
+                                       const double* ops, const int32_t* sides, int32_t site_b, const double* op_b,
+                                       int32_t n_steps, double* out) {
+  if (!h || n_ins < 1 || !offsets || !sites || !ops || !sides) return PT_TEBD_EINVAL;
+  std::vector<Insertion> ins(n_ins);
+  for (int p = 0; p < n_ins; ++p) ins[p] = Insertion{offsets[p], sites[p], sides[p], ops + 8 * p};
+  return correlate_impl(h, ins, site_b, op_b, n_steps, out);
 }
 
 pt_tebd_status pt_tebd_bond_dims(pt_tebd_t h, int32_t* chi, int32_t* xi) {
