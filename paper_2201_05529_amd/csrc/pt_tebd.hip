@@ -743,8 +743,11 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
   } keep{h, err};
   h->oversample = std::max(8, env_int("PT_TEBD_OVERSAMPLE", 64));
   // two power iterations: with one, the leading subspace of D on the N = 21
-  // workload at its chi cap is off by ~1e-6 in the observables
-  h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", 2));
+  // workload at its chi cap is off by ~1e-6 in the observables.  The
+  // FP32-mixed form is held to 1e-4, which one power iteration meets (the
+  // block refinement of small singular values it still needs)
+  const bool mixed = cfg->precision == PT_TEBD_FP32_MIXED;
+  h->power_iters = std::max(0, env_int("PT_TEBD_POWER_ITERS", mixed ? 1 : 2));
   h->cholqr = env_int("PT_TEBD_CHOLQR", 1) != 0;
   // the Gram matrix of a sketch resolves directions down to ~3e-8 of its
   // largest singular value; truncation thresholds below 1e-8 need the
