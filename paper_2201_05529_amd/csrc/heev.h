@@ -495,7 +495,9 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   const int nvec = s_nvec;
 
   // -------- stage 4: eigenvectors of T by twisted factorisations of
-  // L D L^T - mu I (one thread per vector).  Top-down: D+_i = d_i + s_i,
+  // L D L^T - mu I (one thread per vector), the method of Dhillon and
+  // Parlett (Linear Algebra Appl. 387, 2004; the vectors of MRRR without its
+  // representation tree: clusters are handled in stage 4b).  Top-down: D+_i = d_i + s_i,
   // l+_i = l_i d_i / D+_i; bottom-up: D-_i = l_{i-1}^2 d_{i-1} + p_i,
   // u-_i = l_i d_i / D-_{i+1}, p_i = d_i p_{i+1} / D-_{i+1} - mu.  The twist
   // index r minimises |gamma_r| = |s_r + p_r + mu|; z_r = 1 and

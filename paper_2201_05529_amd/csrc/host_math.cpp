@@ -69,7 +69,9 @@ std::vector<cplx> expm(int n, const cplx* a) {
 // H_j^H x = beta e_1, beta real, acting on rows/cols j+1..n-1, so that
 // Q^H A Q = T is real tridiagonal with Q = H_0 H_1 ... H_{n-2}.
 // Tridiagonal stage: implicit-shift QL sweeps (Wilkinson shift) with Givens
-// rotations accumulated into Z; eigenvectors of A are Q Z.
+// rotations accumulated into Z, the tql2 scheme of Bowdler, Martin, Reinsch
+// and Wilkinson (Numer. Math. 11, 1968) written out here; eigenvectors of A
+// are Q Z.
 bool heev(int n, const cplx* ain, double* w, cplx* v) {
   std::vector<cplx> a(ain, ain + static_cast<size_t>(n) * n);
   std::vector<double> d(n, 0.0), e(std::max(n, 1), 0.0);
