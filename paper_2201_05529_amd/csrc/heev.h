@@ -103,7 +103,15 @@ __device__ inline int ldl_negcount(const double* d, const double* lld, int n, do
     double dp = d[i] + s;
     if (fabs(dp) < pivmin) dp = -pivmin;
     cnt += dp < 0.0;
-    s = lld[i] * (s / dp) - sigma;
+    // 1 / dp from the hardware estimate and two Newton steps (a rounding-
+    // level relative perturbation of each step, which the count tolerates
+    // as the factorisation's own rounding), cheaper than a full division
+    double r = __builtin_amdgcn_rcp(dp);
+    double e = fma(-dp, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-dp, r, 1.0);
+    r = fma(r, e, r);
+    s = lld[i] * (s * r) - sigma;
   }
   double dp = d[n - 1] + s;
   if (fabs(dp) < pivmin) dp = -pivmin;
