@@ -67,16 +67,20 @@ class Server:
     together.  max_active: most requests in the batch at once.  max_admit:
     most requests whose PT-MPOs are built in one admission round."""
 
-    def __init__(self, budget_bytes, precision=B.FP32_MIXED, max_active=256, max_admit=64):
-        import torch
-        self.torch = torch
+    def __init__(self, budget_bytes, precision=B.FP32_MIXED, max_active=256, max_admit=64, stream=None):
         self.budget = int(budget_bytes)
         self.precision = precision
         self.max_active = max_active
         self.max_admit = max_admit
-        # the default stream: batches re-formed every few steps issue their
-        # launches directly instead of capturing a graph each time
-        self.stream = torch.cuda.default_stream()
+        if stream is None:
+            import torch
+            # the default stream: batches re-formed every few steps issue
+            # their launches directly instead of capturing a graph each time
+            stream = torch.cuda.default_stream()
+        self.stream = stream
+
+    def _sync(self):
+        self.stream.synchronize()
 
     def _build(self, group):
         """PT-MPOs of a group of requests in one GPU call per (dt, memory
@@ -106,7 +110,6 @@ class Server:
         """requests: list of workload dicts with "arrival_s" and "n_steps".
         Replays the arrivals against the wall clock (realtime) or takes them
         all at time zero.  Returns the list of Result, in request order."""
-        torch = self.torch
         order = sorted(range(len(requests)), key=lambda i: requests[i].get("arrival_s", 0.0) if realtime else 0.0)
         pending = collections.deque(order)
         waiting = collections.deque()
@@ -162,7 +165,7 @@ class Server:
                 batch = B.Batch([a[1] for a in active])
                 dirty = False
             batch.step(1)
-            torch.cuda.synchronize()
+            self._sync()
             finished = []
             for a in active:
                 a[3] -= 1
