@@ -84,6 +84,13 @@ typedef struct {
   int32_t diagonal;
   const double* const* tensors;  /* [n_steps] pointers, complex        */
   const double* const* caps;     /* [n_steps + 1] pointers or NULL     */
+  /* Initially correlated chain site and environment (Appendix A.1: the
+   * augmented legs of the initial MPS have dimension > 1): with
+   * bond_dims[0] > 1, the bath site's initial augmented tensor R[s][e],
+   * complex [d^2][bond_dims[0]] (s the site's Liouville index i d + j of
+   * rho_ij, e the PT-MPO's first bond), which replaces that site's rho0.
+   * NULL (an uncorrelated start) requires bond_dims[0] = 1. */
+  const double* initial;
 } pt_tebd_bath;
 
 typedef struct {

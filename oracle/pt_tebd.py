@@ -91,11 +91,18 @@ def truncation_rank(sv, eps, chi_max=None, tie=TIE_TOLERANCE):
 
 
 class AugmentedMPS:
-    def __init__(self, rho0, d):
+    def __init__(self, rho0, d, initial=None):
+        """Product initial state; ``initial`` maps a bath site to its initial
+        augmented tensor R[s, e] for a chain site initially correlated with
+        its environment (Appendix A.1: augmented legs of dimension > 1 at the
+        start), which replaces that site's rho0."""
         self.d = d
         self.d2 = d * d
         self.n_sites = len(rho0)
         self.gammas = [lv.vec(r).reshape(1, self.d2, 1, 1).copy() for r in rho0]
+        for site, r in (initial or {}).items():
+            r = np.asarray(r, dtype=np.complex128)
+            self.gammas[site] = r.reshape(1, self.d2, r.shape[-1], 1).copy()
         self.lams = [np.ones(1) for _ in range(self.n_sites + 1)]
         self.log_scale = 0.0
         self.step = 0
@@ -223,7 +230,8 @@ class Problem:
             if caps is None:
                 from .ptmpo import caps as make_caps
                 caps = make_caps(bath["tensors"], d)
-            self.baths.append({"site": int(bath["site"]), "tensors": bath["tensors"], "caps": caps})
+            self.baths.append({"site": int(bath["site"]), "tensors": bath["tensors"], "caps": caps,
+                               "initial": bath.get("initial")})
         self.n_sites = len(self.h_site)
         if self.n_sites > 1:
             self.gates = gt.chain_gates(self.h_site, self.h_bond, lindblad, self.dt, d)
@@ -237,7 +245,8 @@ class Engine:
         self.mode = mode
         self.svd_driver = svd_driver
         self.tie = tie
-        self.mps = AugmentedMPS(problem.rho0, problem.d)
+        self.mps = AugmentedMPS(problem.rho0, problem.d,
+                                {b["site"]: b["initial"] for b in problem.baths if b.get("initial") is not None})
         self.stats = []
 
     def _gate(self, mps, bond):

@@ -28,7 +28,8 @@ class Bath(ctypes.Structure):
     _fields_ = [("site", ctypes.c_int32), ("n_steps", ctypes.c_int32),
                 ("bond_dims", ctypes.POINTER(ctypes.c_int32)), ("diagonal", ctypes.c_int32),
                 ("tensors", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
-                ("caps", ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))]
+                ("caps", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+                ("initial", ctypes.POINTER(ctypes.c_double))]
 
 
 class BathParams(ctypes.Structure):
@@ -233,6 +234,13 @@ def _make_config(h_site, h_bond, rho0, dt, baths=(), chi_max=64, xi_max=None, ep
             bs.caps = cptr
         else:
             bs.caps = None
+        if b.get("initial") is not None:
+            # correlated start: the site's initial augmented tensor R[s][e]
+            ini = _cplx(np.asarray(b["initial"], dtype=np.complex128).reshape(4, dims[0]))
+            keep.append(ini)
+            bs.initial = _dptr(ini)
+        else:
+            bs.initial = None
     keep.append(bath_structs)
     cfg.n_baths = len(baths)
     cfg.baths = bath_structs
@@ -257,8 +265,9 @@ def workspace_bytes(h_site, h_bond, rho0, dt, baths=(), chi_max=64, xi_max=None,
 
 class Chain:
     """One PT-TEBD handle.  `baths` is a list of dict(site, tensors, caps
-    (optional)); tensors are P_k[e, e', s] (diagonal) or P_k[e, e', s_out,
-    s_in] complex arrays."""
+    (optional), initial (optional: the site's initial augmented tensor
+    R[s, e] of a correlated start)); tensors are P_k[e, e', s] (diagonal) or
+    P_k[e, e', s_out, s_in] complex arrays."""
 
     def __init__(self, h_site, h_bond, rho0, dt, baths=(), chi_max=64, xi_max=None, eps=1e-7,
                  precision=FP64, lindblad=None, seed=220105529, device=None, stream=None):

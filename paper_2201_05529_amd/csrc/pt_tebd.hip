@@ -337,9 +337,15 @@ pt_tebd_status validate(const pt_tebd_config* cfg, std::string& err) {
     if (b.site < 0 || b.site >= N || used[b.site]) { err = "bath sites must be distinct and in range"; return PT_TEBD_EINVAL; }
     used[b.site] = 1;
     if (b.n_steps < 1 || !b.bond_dims || !b.tensors) { err = "bath needs n_steps >= 1, bond_dims and tensors"; return PT_TEBD_EINVAL; }
-    if (b.bond_dims[0] != 1) { err = "PT-MPO bond_dims[0] must be 1"; return PT_TEBD_EINVAL; }
+    if (b.bond_dims[0] != 1 && !b.initial) {
+      err = "PT-MPO bond_dims[0] > 1 needs the site's initial augmented tensor";
+      return PT_TEBD_EINVAL;
+    }
     for (int k = 0; k <= b.n_steps; ++k)
       if (b.bond_dims[k] < 1 || b.bond_dims[k] > cfg->xi_max) { err = "PT-MPO bond dimension outside [1, xi_max]"; return PT_TEBD_EINVAL; }
+    if (b.initial)
+      for (int q = 0; q < 2 * 4 * b.bond_dims[0]; ++q)
+        if (!std::isfinite(b.initial[q])) { err = "non-finite initial augmented tensor"; return PT_TEBD_EINVAL; }
     const int per = b.diagonal ? 4 : 16;
     for (int k = 0; k < b.n_steps; ++k) {
       if (!b.tensors[k]) { err = "null PT-MPO tensor"; return PT_TEBD_EINVAL; }
@@ -811,7 +817,18 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     for (int n = 0; n < N; ++n)
       for (int s2 = 0; s2 < 4; ++s2)
         g0[(size_t)n * 2 * c.gam_cap + s2] = ptt::mk<double>(cfg->rho0[8 * n + 2 * s2], cfg->rho0[8 * n + 2 * s2 + 1]);
-    std::vector<int> zeros(N, 0), ones(N + 1, 1);
+    std::vector<int> zeros(N, 0), ones(N + 1, 1), xi0(N, 1);
+    // correlated starts: Gamma_n[0][s][e][0] = R[s][e] (compact [a][s][e][b])
+    for (int i = 0; i < cfg->n_baths; ++i) {
+      const pt_tebd_bath& b = cfg->baths[i];
+      if (!b.initial) continue;
+      const int x0 = b.bond_dims[0];
+      xi0[b.site] = x0;
+      for (int s2 = 0; s2 < 4; ++s2)
+        for (int e = 0; e < x0; ++e)
+          g0[(size_t)b.site * 2 * c.gam_cap + (size_t)s2 * x0 + e] =
+              ptt::mk<double>(b.initial[2 * (s2 * x0 + e)], b.initial[2 * (s2 * x0 + e) + 1]);
+    }
     std::vector<double> lam((size_t)(N + 1) * c.chi_cap, 0.0);
     for (int n = 0; n <= N; ++n) lam[(size_t)n * c.chi_cap] = 1.0;
     double zero = 0.0;
@@ -820,7 +837,7 @@ pt_tebd_status create_impl(const pt_tebd_config* cfg, void* ws, size_t bytes, vo
     bool ok = check(hipMemcpyAsync(P.gam[0], g0.data(), g0.size() * sizeof(double2), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.parity[0], zeros.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.chi[0], ones.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
-              check(hipMemcpyAsync(P.xi[0], ones.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
+              check(hipMemcpyAsync(P.xi[0], xi0.data(), N * sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.lam[0], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.log_scale[0], &zero, sizeof(double), hipMemcpyHostToDevice, st), hp, "init") &&
               check(hipMemcpyAsync(P.status[0], &zi, sizeof(int), hipMemcpyHostToDevice, st), hp, "init") &&
@@ -1466,6 +1483,7 @@ pt_tebd_status pt_mpo_build_ohmic(double alpha, double wc, int32_t cutoff_kind, 
   out->bond_dims = bd;
   out->tensors = tp;
   out->caps = nullptr;
+  out->initial = nullptr;
   return PT_TEBD_OK;
 }
 
@@ -1830,6 +1848,7 @@ void fill_bath(int n_steps, const std::vector<int>& dims, const std::vector<std:
   out->bond_dims = bd;
   out->tensors = tp;
   out->caps = nullptr;
+  out->initial = nullptr;
 }
 }  // namespace
 

@@ -24,7 +24,8 @@ def oracle_problem(wl, n_steps=None, form="tempo"):
 def library_chain(wl, prob, precision=0, **kw):
     """Library handle fed with the oracle's PT-MPO tensors and caps."""
     from paper_2201_05529_amd import binding as B
-    baths = [{"site": b["site"], "tensors": b["tensors"], "caps": b["caps"]} for b in prob.baths]
+    baths = [{"site": b["site"], "tensors": b["tensors"], "caps": b["caps"], "initial": b.get("initial")}
+             for b in prob.baths]
     xi = max([max(p.shape[1] for p in b["tensors"]) for b in prob.baths] + [1])
     return B.Chain(wl["h_site"], wl["h_bond"], wl["rho0"], wl["dt"], baths=baths,
                    chi_max=wl["chi_max"], xi_max=max(xi, 1), eps=wl["eps"], precision=precision,

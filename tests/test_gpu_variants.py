@@ -1,7 +1,8 @@
 """GPU parity for the model variants the method covers beyond sigma^z
 coupling: baths coupled through non-diagonal operators (sigma^y, sigma^x:
 the PT-MPO tensors are dense in the system index, Sec. III.A), GKSL
-dissipators in the chain propagators (Appendix A.1), and both at once.
+dissipators in the chain propagators (Appendix A.1), both at once, and a
+chain site that starts correlated with its environment (Appendix A.1).
 The library is fed the oracle's PT-MPO tensors; observables within 1e-6 of
 the oracle (FP64) and 1e-4 (FP32-mixed)."""
 import numpy as np
@@ -76,3 +77,46 @@ def test_gksl_and_dense_coupling_together():
     lind = [[np.sqrt(0.15) * SM], [], [np.sqrt(0.05) * SZ]]
     wl = _chain(3, [W.bath(1, 0.12, 4.0, 1.5, 3, coupling=SY)], lindblad=lind)
     _check(wl, 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_correlated_initial_state(precision):
+    # site 0 starts entangled with an ancilla-qubit environment whose exact
+    # PT-MPO (the joint propagator, bond = the ancilla's Liouville index)
+    # the oracle's pin checks against dense evolution of chain plus ancilla
+    from paper_2201_05529_amd import binding as B
+    from tests.test_oracle_correlated_start import ancilla_model, chain, joint_to_augmented
+    print(f"correlated start precision={precision}", flush=True)
+    dt, m = 0.1, 8
+    tensors, _ = ancilla_model(dt, m)
+    phi = np.array([1, 0, 0, 1], dtype=np.complex128) / np.sqrt(2)
+    r0 = joint_to_augmented(0.7 * np.outer(phi, phi.conj()) + 0.3 * np.eye(4) / 4)
+    h_site, h_bond = chain()
+    down = np.diag([0.0, 1.0]).astype(np.complex128)
+    rho0 = [np.eye(2) / 2, down]
+    eng = opt.Engine(opt.Problem(h_site, h_bond, rho0, dt, baths=[{"site": 0, "tensors": tensors, "initial": r0}],
+                                 eps=1e-14))
+    ch = B.Chain(h_site, h_bond, rho0, dt, baths=[{"site": 0, "tensors": tensors, "initial": r0}], chi_max=16,
+                 xi_max=4, eps=1e-14, precision=precision)
+    err = 0.0
+    for k in range(m + 1):
+        if k:
+            ch.step(1)
+            eng.step(1)
+        v, tr = ch.observe([0, 1, 0, 1], np.array([SZ, SZ, SX, SX]))
+        ref = np.array([eng.expectation(0, SZ), eng.expectation(1, SZ), eng.expectation(0, SX),
+                        eng.expectation(1, SX)])
+        err = max(err, float(np.abs(v - ref).max()), abs(tr - eng.trace()))
+    ch.close()
+    print(f"  max error {err:.1e}", flush=True)
+    assert err < TOL[precision]
+
+
+def test_correlated_start_needs_its_tensor():
+    from paper_2201_05529_amd import binding as B
+    from tests.test_oracle_correlated_start import ancilla_model, chain
+    tensors, _ = ancilla_model(0.1, 4)
+    h_site, h_bond = chain()
+    with pytest.raises(B.PtTebdError):
+        B.Chain(h_site, h_bond, [np.eye(2) / 2] * 2, 0.1, baths=[{"site": 0, "tensors": tensors}], chi_max=16,
+                xi_max=4)
