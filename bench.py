@@ -101,7 +101,9 @@ def kernel_roofline(kind, ms_total, launches, flops):
     peak = PEAK_TFLOPS["fp64"]  # the eigensolver runs FP64 vector arithmetic in both forms
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic_from_profiles(kind),
-            "kernel": {"eigensolver": "heev_solve_kernel", "gemm": "k_bond_gemm"}[kind],
+            # the eigensolver's timed region: its tridiagonal reduction and
+            # stages 2-4, two kernels launched back to back on the stream
+            "kernel": {"eigensolver": "heev_tridiag_kernel+heev_solve_kernel", "gemm": "k_bond_gemm"}[kind],
             "launches": launches, "avg_launch_ms": ms_total / launches, "alg_flops_per_launch": flops / launches}
 
 

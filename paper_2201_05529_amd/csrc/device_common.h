@@ -43,6 +43,45 @@ __device__ inline double warp_sum(double v) {
   return v;
 }
 
+// Sum over a fully active wave by DPP lane moves (quad permutations, row
+// rotations, row broadcasts): register-to-register, no LDS round trip.  The
+// total is read from lane 63 and returned to every lane.
+template <int CTRL, int ROW_MASK> __device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_move<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]: every lane holds its quad's sum
+  v += dpp_move<0x124, 0xF>(v);   // row_ror 4
+  v += dpp_move<0x128, 0xF>(v);   // row_ror 8: every lane holds its row's sum
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast 15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);   // row_bcast 31 into rows 2 and 3: lane 63 holds the total
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Loads and stores through pointers known to be in global memory.  A
+// pointer read from a job descriptor has no address space for the compiler,
+// which then emits flat instructions; those count against the LDS counter as
+// well, so every LDS wait (and every barrier) also waits for them.
+#define PTT_GLOBAL __attribute__((address_space(1)))
+typedef double ptt_d2v __attribute__((ext_vector_type(2)));
+__device__ inline double2 gload(const double2* p) {
+  const ptt_d2v v = *(const PTT_GLOBAL ptt_d2v*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ inline void gstore(double2* p, double2 v) {
+  ptt_d2v t;
+  t.x = v.x;
+  t.y = v.y;
+  *(PTT_GLOBAL ptt_d2v*)p = t;
+}
+__device__ inline void gstore(double* p, double v) { *(PTT_GLOBAL double*)p = v; }
+
 // Block-wide sum of one double (all threads get the result).  `red` must
 // hold one double per wave.
 __device__ inline double block_sum(double v, double* red) {

@@ -119,10 +119,297 @@ __device__ inline int ldl_negcount(const double* d, const double* lld, int n, do
   return cnt;
 }
 
-// ------------------------------------------------------------- stage 1..4
+// ------------------------------------------------------------- stage 1
+// Reduction to real tridiagonal form, T = Q^H A Q (its own kernel, one
+// workgroup per problem; writes d, e, tau and the reflectors).
+//
+// Both triangles of the trailing block are kept.  The rank-2 update of step
+// j is not applied at once: step j+1 first forms its own row from the
+// pending update, then one fused pass over the trailing block applies the
+// pending update and accumulates the next matrix-vector product, so every
+// element is visited once per step.  Each element needs three entries of
+// the step's vectors (w_r, v_r of the pending update and the new reflector
+// v_r) that are the same for the whole row; a thread owns two columns, so
+// each such LDS read serves two elements.  While the trailing
+// block is larger than TRI_RES the pass reads and writes it in global
+// memory, coalesced along rows, TRI_DEPTH rows of loads in flight per
+// thread.  Once it fits, the block moves into registers (wave w holds rows
+// w + 8 k, lane l columns 2 l and 2 l + 1: 128 registers per thread, which
+// eight waves of 256 registers hold without spilling) and the remaining
+// steps touch no memory but the vectors in LDS; the row that the next step
+// reflects is handed over through LDS.
+constexpr int HEEV_TRI_THREADS = 512;
+constexpr int TRI_RES = 128;
+constexpr int TRI_WAVES = HEEV_TRI_THREADS / 64;
+constexpr int TRI_RES_ROWS = TRI_RES / TRI_WAVES;
+constexpr int TRI_DEPTH = 4;
+
 // flops (may be null): accumulates the algorithmic flop count of the
-// tridiagonal reduction, 16 n^3 / 3 per complex Hermitian matrix.
-__global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const HeevJob* jobs, double* flops) {
+// reduction, 16 n^3 / 3 per complex Hermitian matrix.
+__global__ void __launch_bounds__(HEEV_TRI_THREADS) heev_tridiag_kernel(const HeevJob* jobs, double* flops) {
+  constexpr int NT = HEEV_TRI_THREADS;
+  const HeevJob& J = jobs[blockIdx.x];
+  const int n = *J.n_ptr;
+  const int tid = threadIdx.x;
+  if (n > J.n_cap || n <= 0) return;  // the solve kernel reports a size beyond the workspace
+  if (flops && tid == 0) atomicAdd(flops, 16.0 / 3.0 * (double)n * n * n);
+  if (J.stamps && tid == 0) J.stamps[0] = wall_clock64();
+  __shared__ double2 vbuf[2][1024];
+  __shared__ double2 sy[1024];      // tau A v of the pending step (w = y - half v)
+  __shared__ double2 part[1024];    // partial matrix-vector sums [groups][m]
+  __shared__ double2 rowbuf[TRI_RES];
+  __shared__ double s_dd[1024], s_ee[1024];   // T, written out at the end
+  __shared__ double2 s_tau[1024];
+  __shared__ double s_sig[TRI_WAVES];    // |x|^2 below the first entry, per wave
+  __shared__ double2 s_vhy[TRI_WAVES];   // v^H y, per wave
+  __shared__ double2 s_alpha;
+  double2* A = J.a;
+  const int lda = J.lda;
+  const int nc = J.n_cap;
+  // the wave index, known to the compiler as uniform across the wave
+  const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double2* vp = vbuf[0];          // pending v (offset j at step j)
+  double2* vc = vbuf[1];          // current v
+  double half = 0.0;              // of the pending step
+  // before the first step the pending update is zero (w = 0, v = 0)
+  for (int i = tid; i < 1024; i += NT) {
+    vp[i] = mk<double>(0.0, 0.0);
+    sy[i] = mk<double>(0.0, 0.0);
+  }
+  __syncthreads();
+
+  // w_i of the pending update, w = y - half v
+  auto wpend = [&](int i) { return csub<double>(sy[i], cscale<double>(vp[i], half)); };
+  // val -= w_r conj(v_c) + v_r conj(w_c), as eight fused multiply-adds
+  auto update = [&](double2& val, double2 wr, double2 vr, double2 wc, double2 vcol) {
+    val.x = fma(-wr.x, vcol.x, val.x);
+    val.x = fma(-wr.y, vcol.y, val.x);
+    val.x = fma(-vr.x, wc.x, val.x);
+    val.x = fma(-vr.y, wc.y, val.x);
+    val.y = fma(-wr.y, vcol.x, val.y);
+    val.y = fma(wr.x, vcol.y, val.y);
+    val.y = fma(-vr.y, wc.x, val.y);
+    val.y = fma(vr.x, wc.y, val.y);
+  };
+
+  // (a) row j of the updated matrix (row(i) = A_j,j+1+i, row(-1) the
+  // diagonal, before the pending update); x = conj(row) below the diagonal;
+  // (b) the reflector, computed redundantly by every thread, into vc.
+  // Per-wave partial sums are added in a fixed order (bit-reproducible):
+  // lane q takes wave q's, then a DPP sum over the wave.
+  auto reflect = [&](int j, auto row) {
+    const int m = n - j - 1;
+    double p2 = 0.0;
+    for (int i = tid; i < m; i += NT) {
+      double2 val = row(i);
+      update(val, wpend(0), vp[0], wpend(i + 1), vp[i + 1]);
+      const double2 x = cconj<double>(val);
+      vc[i] = x;
+      if (i == 0) s_alpha = x;
+      else p2 += cabs2<double>(x);
+    }
+    p2 = wave_sum_dpp(p2);
+    if (lane == 0) s_sig[wid] = p2;
+    if (tid == 0) {
+      const double2 w0 = wpend(0);
+      s_dd[j] = row(-1).x - 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
+    }
+    __syncthreads();
+    const double sig2 = wave_sum_dpp(lane < TRI_WAVES ? s_sig[lane] : 0.0);
+    const double2 alpha = s_alpha;
+    double2 tau = mk<double>(0.0, 0.0);
+    double beta = alpha.x;
+    if (!(sig2 == 0.0 && alpha.y == 0.0)) {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
+      beta = alpha.x >= 0.0 ? -nrm : nrm;
+      const double ib = 1.0 / beta;
+      tau = mk<double>((beta - alpha.x) * ib, -alpha.y * ib);
+    }
+    const bool active = !(tau.x == 0.0 && tau.y == 0.0);
+    double2 scal = mk<double>(0.0, 0.0);
+    {
+      const double2 den = mk<double>(alpha.x - beta, alpha.y);
+      const double dn = den.x * den.x + den.y * den.y;
+      if (active && dn > 0.0) {
+        const double idn = 1.0 / dn;
+        scal = mk<double>(den.x * idn, -den.y * idn);
+      }
+    }
+    if (tid == 0) {
+      s_tau[j] = tau;
+      s_ee[j] = beta;
+    }
+    for (int i = tid; i < m; i += NT) {
+      const double2 vi = (i == 0) ? mk<double>(1.0, 0.0)
+                                  : (active ? cmul<double>(vc[i], scal) : mk<double>(0.0, 0.0));
+      vc[i] = vi;
+      gstore(J.refl + (size_t)j * nc + i, vi);
+    }
+    __syncthreads();
+    return tau;
+  };
+
+  // (d) y = tau A22 v from the partial sums (kept in sy), v^H y; the
+  // update w = y - 1/2 Re(conj(tau) v^H y) v becomes the pending one
+  auto finish = [&](int m, int groups, double2 tau) {
+    double2 pv = mk<double>(0.0, 0.0);
+    for (int i = tid; i < m; i += NT) {
+      double2 y = mk<double>(0.0, 0.0);
+      for (int q = 0; q < groups; ++q) y = cadd<double>(y, part[q * m + i]);
+      y = cmul<double>(tau, y);
+      sy[i] = y;
+      cfmaconj<double>(pv, vc[i], y);
+    }
+    pv.x = wave_sum_dpp(pv.x);
+    pv.y = wave_sum_dpp(pv.y);
+    if (lane == 0) s_vhy[wid] = pv;
+    __syncthreads();
+    const double2 q = lane < TRI_WAVES ? s_vhy[lane] : mk<double>(0.0, 0.0);
+    const double2 vhy = mk<double>(wave_sum_dpp(q.x), wave_sum_dpp(q.y));
+    half = 0.5 * (tau.x * vhy.x + tau.y * vhy.y);
+    double2* t = vp;
+    vp = vc;
+    vc = t;
+  };
+
+  // steps with a trailing block larger than TRI_RES: global memory
+  const int j0 = max(0, n - TRI_RES);
+  for (int j = 0; j < j0; ++j) {
+    const int m = n - j - 1, off = j + 1;
+    const double2* arow = A + (size_t)j * lda + off;
+    const double2 tau = reflect(j, [&](int i) { return gload(arow + i); });
+    // (c) fused pass: A22 -= pending update; part = conj(A22)^T v.  Thread
+    // (g, p) owns columns p and p + mp of A22 (the second one only if m is
+    // larger), so each load and store instruction covers contiguous
+    // columns, and rows g, g + groups, ...
+    const int mp = (m + 1) >> 1;
+    const int groups = max(1, NT / mp);
+    const int p = tid % mp, g = tid / mp;
+    if (g < groups) {
+      const int c0 = p, c1 = min(p + mp, m - 1);
+      const bool two = p + mp < m;
+      double2 acc0 = mk<double>(0.0, 0.0), acc1 = mk<double>(0.0, 0.0);
+      double2* base = A + (size_t)off * lda + off;
+      const double2 wc0 = wpend(c0 + 1), vc0 = vp[c0 + 1], wc1 = wpend(c1 + 1), vc1 = vp[c1 + 1];
+      // two batches of TRI_DEPTH rows in flight: the next batch is loaded
+      // while the current one is updated.  Loads of rows past the end
+      // re-read the last row (no branch around a load); only the rows
+      // inside are updated and summed
+      const int stride = TRI_DEPTH * groups;
+      auto load_batch = [&](int r0, double2* x0, double2* x1) {
+#pragma unroll
+        for (int u = 0; u < TRI_DEPTH; ++u) {
+          const int r = min(r0 + u * groups, m - 1);
+          x0[u] = gload(base + r * lda + c0);
+          x1[u] = gload(base + r * lda + c1);
+        }
+      };
+      auto run_batch = [&](int r0, double2* x0, double2* x1) {
+#pragma unroll
+        for (int u = 0; u < TRI_DEPTH; ++u) {
+          const int r = r0 + u * groups;
+          if (r < m) {
+            const double2 vr = vc[r];
+            const double2 wr = wpend(r + 1), pr = vp[r + 1];
+            update(x0[u], wr, pr, wc0, vc0);
+            update(x1[u], wr, pr, wc1, vc1);
+            gstore(base + r * lda + c0, x0[u]);
+            if (two) gstore(base + r * lda + c1, x1[u]);
+            cfmaconj<double>(acc0, x0[u], vr);
+            cfmaconj<double>(acc1, x1[u], vr);
+          }
+        }
+      };
+      double2 a0[TRI_DEPTH], a1[TRI_DEPTH], b0[TRI_DEPTH], b1[TRI_DEPTH];
+      int r0 = g;
+      load_batch(r0, a0, a1);
+      while (r0 < m) {
+        load_batch(r0 + stride, b0, b1);
+        run_batch(r0, a0, a1);
+        r0 += stride;
+        if (r0 >= m) break;
+        load_batch(r0 + stride, a0, a1);
+        run_batch(r0, b0, b1);
+        r0 += stride;
+      }
+      part[g * m + c0] = acc0;
+      if (two) part[g * m + c1] = acc1;
+    }
+    __syncthreads();
+    finish(m, groups, tau);
+  }
+
+  // the trailing block [j0, n)^2 (updated up to the pending step) into
+  // registers: ar[k][h] = A_(j0 + wid + 8 k),(j0 + 2 lane + h)
+  const int nr = n - j0;
+  double2 ar[TRI_RES_ROWS][2];
+#pragma unroll
+  for (int k = 0; k < TRI_RES_ROWS; ++k) {
+    const int r = wid + TRI_WAVES * k;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 2 * lane + h;
+      ar[k][h] = (r < nr && c < nr) ? gload(A + (size_t)(j0 + r) * lda + j0 + c) : mk<double>(0.0, 0.0);
+    }
+  }
+  if (wid == 0) {
+    if (2 * lane < nr) rowbuf[2 * lane] = ar[0][0];
+    if (2 * lane + 1 < nr) rowbuf[2 * lane + 1] = ar[0][1];
+  }
+  __syncthreads();
+  for (int j = j0; j + 1 < n; ++j) {
+    const int m = n - j - 1, ol = j + 1 - j0;   // ol: first row / column of A22 in the block
+    const double2 tau = reflect(j, [&](int i) { return rowbuf[ol + i]; });
+    // (c) on the registers: lane columns 2 lane + h are A22 columns
+    // cc_h = 2 lane + h - ol; the first row of A22 goes to rowbuf
+    const int cc0 = 2 * lane - ol, cc1 = cc0 + 1;
+    const bool ok0 = cc0 >= 0 && cc0 < m, ok1 = cc1 >= 0 && cc1 < m;
+    if (ok0 || ok1) {
+      double2 acc0 = mk<double>(0.0, 0.0), acc1 = mk<double>(0.0, 0.0);
+      // a column outside A22 reads index 0 and is never stored
+      const int i0 = ok0 ? cc0 + 1 : 0, i1 = ok1 ? cc1 + 1 : 0;
+      const double2 wc0 = wpend(i0), vc0 = vp[i0], wc1 = wpend(i1), vc1 = vp[i1];
+#pragma unroll
+      for (int k = 0; k < TRI_RES_ROWS; ++k) {
+        const int rr = wid + TRI_WAVES * k - ol;   // row of A22, the same for the whole wave
+        if (rr >= 0 && rr < m) {
+          const double2 vr = vc[rr];
+          const double2 wr = wpend(rr + 1), pr = vp[rr + 1];
+          update(ar[k][0], wr, pr, wc0, vc0);
+          update(ar[k][1], wr, pr, wc1, vc1);
+          if (rr == 0) {
+            if (ok0) rowbuf[ol + cc0] = ar[k][0];
+            if (ok1) rowbuf[ol + cc1] = ar[k][1];
+          }
+          cfmaconj<double>(acc0, ar[k][0], vr);
+          cfmaconj<double>(acc1, ar[k][1], vr);
+        }
+      }
+      if (ok0) part[wid * m + cc0] = acc0;
+      if (ok1) part[wid * m + cc1] = acc1;
+    }
+    __syncthreads();
+    finish(m, TRI_WAVES, tau);
+  }
+  if (tid == 0) {
+    const double2 w0 = wpend(0);
+    s_dd[n - 1] = (n > 1 ? rowbuf[nr - 1].x : gload(A).x) - 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
+    s_ee[n - 1] = 0.0;
+    s_tau[n - 1] = mk<double>(0.0, 0.0);
+  }
+  __syncthreads();
+  // T and the reflector scalars: d, e, tau (re, im)
+  for (int i = tid; i < n; i += NT) {
+    gstore(J.tri + i, s_dd[i]);
+    gstore(J.tri + nc + i, s_ee[i]);
+    gstore(reinterpret_cast<double2*>(J.tri + 2 * nc) + i, s_tau[i]);
+  }
+  if (J.stamps && tid == 0) J.stamps[1] = wall_clock64();
+}
+
+// ------------------------------------------------------------- stage 2..4
+// After heev_tridiag_kernel on the same jobs: d, e of T are in J.tri.
+__global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const HeevJob* jobs) {
   constexpr int NT = HEEV_SOLVE_THREADS;
   const HeevJob& J = jobs[blockIdx.x];
   const int n = *J.n_ptr;
@@ -132,166 +419,19 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     return;
   }
   if (n <= 0) return;  // nothing to do; *nvec_out is left as it is
-  if (flops && tid == 0) atomicAdd(flops, 16.0 / 3.0 * (double)n * n * n);
   auto stamp = [&](int i) {
     if (J.stamps && tid == 0) J.stamps[i] = wall_clock64();
   };
-  stamp(0);
-  __shared__ double buf[8192];     // stage 1: two v, w, partial sums; later: d, l, l d, l^2 d, mu, tau
+  __shared__ double buf[8192];     // d, l, l d, l^2 d, mu, tau, inverse-iteration scratch
   __shared__ double red[NT / 64];
   __shared__ double2 s_tau;
   __shared__ double s_beta, s_delta, s_tnorm;
   __shared__ int s_nvec, s_ok, s_nb, s_nref;
   __shared__ int s_bs[1025];  // block b of T covers rows [s_bs[b], s_bs[b + 1])
   __shared__ int s_kb[1024];  // block of the eigenvalue mu[j] (ascending order)
-  double2* A = J.a;
-  const int lda = J.lda;
   const int nc = J.n_cap;
   double* dd = J.tri;              // diagonal of T
   double* ee = J.tri + nc;         // off-diagonal of T (ee[i] couples i, i+1)
-  double2* taus = reinterpret_cast<double2*>(J.tri + 2 * nc);
-
-  // -------- stage 1: reduction to real tridiagonal form, T = Q^H A Q.
-  // Both triangles of the trailing block are kept.  The rank-2 update of
-  // step j is not applied at once: step j+1 first forms its own row from the
-  // pending update, then one fused pass over the trailing block applies the
-  // pending update and accumulates the next matrix-vector product, so every
-  // element is read and written once per step.  Each pass is coalesced
-  // along rows (thread c of a row group owns column c).
-  {
-    double2* vbuf0 = reinterpret_cast<double2*>(buf);
-    double2* vbuf1 = vbuf0 + 1024;
-    double2* sy = vbuf1 + 1024;   // tau A v of the pending step (w = y - half v)
-    double2* part = sy + 1024;
-    double2* vp = vbuf0;          // pending v (offset j at step j)
-    double2* vc = vbuf1;          // current v
-    // per-wave partial sums, added in a fixed order (bit-reproducible)
-    __shared__ double s_sig[NT / 64];       // |x|^2 below the first entry
-    __shared__ double2 s_vhy[NT / 64];      // v^H y
-    __shared__ double2 s_alpha;
-    const int lane = tid & 63, wid = tid >> 6;
-    bool pending = false;
-    double half = 0.0;            // of the pending step
-    for (int j = 0; j + 1 < n; ++j) {
-      const int m = n - j - 1, off = j + 1;
-      // (a) row j of the updated matrix; x = conj(row) below the diagonal
-      double p2 = 0.0;
-      for (int i = tid; i < m; i += NT) {
-        double2 val = A[(size_t)j * lda + off + i];
-        if (pending) {
-          const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
-          const double2 wi = csub<double>(sy[i + 1], cscale<double>(vp[i + 1], half));
-          const double2 t1 = cmul<double>(w0, cconj<double>(vp[i + 1]));
-          const double2 t2 = cmul<double>(vp[0], cconj<double>(wi));
-          val.x -= t1.x + t2.x;
-          val.y -= t1.y + t2.y;
-        }
-        const double2 x = cconj<double>(val);
-        vc[i] = x;
-        if (i == 0) s_alpha = x;
-        else p2 += cabs2<double>(x);
-      }
-      p2 = warp_sum(p2);
-      if (lane == 0) s_sig[wid] = p2;
-      if (tid == 0) {
-        double a = A[(size_t)j * lda + j].x;
-        if (pending) {
-          const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
-          a -= 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
-        }
-        dd[j] = a;
-      }
-      __syncthreads();
-      // (b) reflector, computed redundantly by every thread
-      double sig2 = 0.0;
-      for (int q = 0; q < NT / 64; ++q) sig2 += s_sig[q];
-      const double2 alpha = s_alpha;
-      double2 tau = mk<double>(0.0, 0.0);
-      double beta = alpha.x;
-      if (!(sig2 == 0.0 && alpha.y == 0.0)) {
-        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig2);
-        beta = alpha.x >= 0.0 ? -nrm : nrm;
-        tau = mk<double>((beta - alpha.x) / beta, -alpha.y / beta);
-      }
-      const bool active = !(tau.x == 0.0 && tau.y == 0.0);
-      double2 scal = mk<double>(0.0, 0.0);
-      {
-        const double2 den = mk<double>(alpha.x - beta, alpha.y);
-        const double dn = den.x * den.x + den.y * den.y;
-        if (active && dn > 0.0) scal = mk<double>(den.x / dn, -den.y / dn);
-      }
-      if (tid == 0) {
-        taus[j] = tau;
-        ee[j] = beta;
-      }
-      for (int i = tid; i < m; i += NT) {
-        const double2 vi = (i == 0) ? mk<double>(1.0, 0.0)
-                                    : (active ? cmul<double>(vc[i], scal) : mk<double>(0.0, 0.0));
-        vc[i] = vi;
-        J.refl[(size_t)j * nc + i] = vi;
-      }
-      __syncthreads();
-      // (c) fused pass: A22 -= pending update; part = conj(A22)^T v
-      const int groups = max(1, NT / m);
-      const int c = tid % m, g = tid / m;
-      if (g < groups) {
-        double2 acc = mk<double>(0.0, 0.0);
-        if (pending) {
-          const double2 wpc = cconj<double>(csub<double>(sy[c + 1], cscale<double>(vp[c + 1], half)));
-          const double2 vpc = cconj<double>(vp[c + 1]);
-#pragma unroll 4
-          for (int r = g; r < m; r += groups) {
-            double2* dst = A + (size_t)(off + r) * lda + off + c;
-            double2 val = *dst;
-            const double2 wr = csub<double>(sy[r + 1], cscale<double>(vp[r + 1], half));
-            const double2 t1 = cmul<double>(wr, vpc);
-            const double2 t2 = cmul<double>(vp[r + 1], wpc);
-            val.x -= t1.x + t2.x;
-            val.y -= t1.y + t2.y;
-            *dst = val;
-            cfmaconj<double>(acc, val, vc[r]);
-          }
-        } else {
-#pragma unroll 4
-          for (int r = g; r < m; r += groups) cfmaconj<double>(acc, A[(size_t)(off + r) * lda + off + c], vc[r]);
-        }
-        part[g * m + c] = acc;
-      }
-      __syncthreads();
-      // (d) y = tau A22 v (kept in sy); v^H y
-      double2 pv = mk<double>(0.0, 0.0);
-      if (tid < m) {
-        double2 y = mk<double>(0.0, 0.0);
-        for (int q = 0; q < groups; ++q) y = cadd<double>(y, part[q * m + tid]);
-        y = cmul<double>(tau, y);
-        sy[tid] = y;
-        cfmaconj<double>(pv, vc[tid], y);
-      }
-      pv.x = warp_sum(pv.x);
-      pv.y = warp_sum(pv.y);
-      if (lane == 0) s_vhy[wid] = pv;
-      __syncthreads();
-      // w = y - 1/2 Re(conj(tau) v^H y) v becomes the pending update
-      double2 vhy = mk<double>(0.0, 0.0);
-      for (int q = 0; q < NT / 64; ++q) vhy = cadd<double>(vhy, s_vhy[q]);
-      half = 0.5 * (tau.x * vhy.x + tau.y * vhy.y);
-      double2* t = vp;
-      vp = vc;
-      vc = t;
-      pending = true;
-    }
-    if (tid == 0) {
-      double a = A[(size_t)(n - 1) * lda + (n - 1)].x;
-      if (pending) {
-        const double2 w0 = csub<double>(sy[0], cscale<double>(vp[0], half));
-        a -= 2.0 * (w0.x * vp[0].x + w0.y * vp[0].y);
-      }
-      dd[n - 1] = a;
-      ee[n - 1] = 0.0;
-    }
-  }
-  __syncthreads();
-  stamp(1);
 
   // -------- stage 2: T + delta I = L D L^T with D > 0
   double* d = buf;

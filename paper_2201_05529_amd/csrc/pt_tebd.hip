@@ -460,8 +460,10 @@ int elem_blocks(long long n);
 // passes: block Gram-Schmidt passes of stage 6 (2), or 0 where the caller
 // re-orthonormalises the vectors anyway (then only the column scaling)
 void launch_heev(hipStream_t st, const HeevJob* jobs, int n_jobs, int n_cap, int passes = 2) {
+  // the timed eigensolver region: tridiagonal reduction and stages 2-4
   const bool t = timed_begin(KT_EIGENSOLVER, st);
-  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs, timed_flops(KT_EIGENSOLVER));
+  ptt::heev_tridiag_kernel<<<n_jobs, ptt::HEEV_TRI_THREADS, 0, st>>>(jobs, timed_flops(KT_EIGENSOLVER));
+  ptt::heev_solve_kernel<<<n_jobs, ptt::HEEV_SOLVE_THREADS, 0, st>>>(jobs);
   timed_end(t, st);
   dim3 grid((n_cap + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, n_jobs);
   const size_t shm = (size_t)n_cap * ptt::HEEV_BT_COLS * sizeof(double2);
@@ -2144,7 +2146,8 @@ extern "C" pt_tebd_status pt_test_heev_profile(int32_t n, const double* a, int32
     for (int rep = 0; rep < reps && ok; ++rep) {
       ok = hipMemcpy(da, da0, nn * sizeof(double2), hipMemcpyDeviceToDevice) == hipSuccess;
       hipEventRecord(e0, nullptr);
-      ptt::heev_solve_kernel<<<1, ptt::HEEV_SOLVE_THREADS, 0, nullptr>>>(djob, nullptr);
+      ptt::heev_tridiag_kernel<<<1, ptt::HEEV_TRI_THREADS, 0, nullptr>>>(djob, nullptr);
+      ptt::heev_solve_kernel<<<1, ptt::HEEV_SOLVE_THREADS, 0, nullptr>>>(djob);
       hipEventRecord(e1, nullptr);
       // back-transformation and the two orthonormalisation passes
       dim3 grid((n + ptt::HEEV_BT_COLS - 1) / ptt::HEEV_BT_COLS, 1);
