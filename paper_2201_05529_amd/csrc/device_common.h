@@ -64,6 +64,17 @@ __device__ inline double wave_sum_dpp(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Sum over each half of a fully active wave (lanes 0-31, 32-63) by DPP
+// moves; the half's total is valid in its last lane (31 or 63).
+__device__ inline double half_wave_sum_dpp(double v) {
+  v += dpp_move<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x124, 0xF>(v);   // row_ror 4
+  v += dpp_move<0x128, 0xF>(v);   // row_ror 8: every lane holds its row's sum
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast 15 into rows 1 and 3
+  return v;
+}
+
 // Loads and stores through pointers known to be in global memory.  A
 // pointer read from a job descriptor has no address space for the compiler,
 // which then emits flat instructions; those count against the LDS counter as

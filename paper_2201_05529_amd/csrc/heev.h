@@ -1039,8 +1039,13 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
 // --------------------------------------------------------------- stage 5
 // V = Q Z for the selected columns; Q = H_0 H_1 ... H_{n-2}, so the
 // reflectors are applied in the order H_{n-2}, ..., H_0.  Each workgroup
-// keeps a chunk of HEEV_BT_COLS columns in LDS.
+// keeps a chunk of HEEV_BT_COLS columns in LDS.  The application is a chain
+// of n - 1 dependent steps, so nothing the next step needs from global
+// memory waits on the chain: every tau sits in LDS from the start, and the
+// next reflector's entries (up to HEEV_BT_PF per lane, which covers n <= 257)
+// are loaded into registers while the current one is applied.
 constexpr int HEEV_BT_COLS = 8;
+constexpr int HEEV_BT_PF = 8;
 
 __global__ void __launch_bounds__(HEEV_THREADS) heev_backtransform_kernel(const HeevJob* jobs) {
   const HeevJob& J = jobs[blockIdx.y];
@@ -1050,46 +1055,78 @@ __global__ void __launch_bounds__(HEEV_THREADS) heev_backtransform_kernel(const 
   const int c0 = blockIdx.x * HEEV_BT_COLS;
   if (c0 >= nvec) return;
   const int ncol = min(HEEV_BT_COLS, nvec - c0);
-  extern __shared__ double2 zs[];  // [n][HEEV_BT_COLS]
+  extern __shared__ double2 zs[];  // [HEEV_BT_COLS][n]: a column's lanes read consecutive entries
   __shared__ double2 dots[1][HEEV_BT_COLS];
+  __shared__ double2 s_tau[1024];
   const int tid = threadIdx.x;
   const int nc = J.n_cap;
   for (int e = tid; e < n * HEEV_BT_COLS; e += HEEV_THREADS) {
     const int i = e / HEEV_BT_COLS, c = e - i * HEEV_BT_COLS;
-    zs[e] = mk<double>(c < ncol ? J.z[(size_t)i * nc + c0 + c] : 0.0, 0.0);
+    zs[c * n + i] = mk<double>(c < ncol ? J.z[(size_t)i * nc + c0 + c] : 0.0, 0.0);
   }
   const double2* taus = reinterpret_cast<const double2*>(J.tri + 2 * J.n_cap);
+  for (int i = tid; i + 1 < n; i += HEEV_THREADS) s_tau[i] = gload(taus + i);
   // 32 lanes per column: thread (c, l) owns rows l, l + 32, ... of column c
-  // below the reflector's start, so a column's dot product is one reduction
-  // over half a wave (five shuffles per real part) with no cross-wave sum
+  // below the reflector's start, so a column's dot product is one DPP sum
+  // over half a wave with no cross-wave sum
   constexpr int LPC = HEEV_THREADS / HEEV_BT_COLS;  // 32
   const int cc = tid / LPC, ll = tid % LPC;
-  __syncthreads();
-  for (int j = n - 2; j >= 0; --j) {
-    const double2 tau = taus[j];
-    if (tau.x == 0.0 && tau.y == 0.0) continue;
+  double2* zc = zs + cc * n;  // this thread's column
+  // entries i = ll + LPC t (t < HEEV_BT_PF) of reflector j, zero past its end
+  auto fetch = [&](int j, double2* dst) {
+    const int m = n - j - 1;
+    const double2* v = J.refl + (size_t)max(j, 0) * nc;
+#pragma unroll
+    for (int t = 0; t < HEEV_BT_PF; ++t) {
+      const int i = ll + LPC * t;
+      dst[t] = (j >= 0 && i < m) ? gload(v + i) : mk<double>(0.0, 0.0);
+    }
+  };
+  auto apply = [&](int j, const double2* vr) {
+    const double2 tau = s_tau[j];
+    if (tau.x == 0.0 && tau.y == 0.0) return;
     const int m = n - j - 1;
     const double2* v = J.refl + (size_t)j * nc;
     // s_c = tau * sum_i conj(v_i) z[j+1+i][c]
     double2 part = mk<double>(0.0, 0.0);
-    for (int i = ll; i < m; i += LPC) cfmaconj<double>(part, v[i], zs[(j + 1 + i) * HEEV_BT_COLS + cc]);
 #pragma unroll
-    for (int off = LPC / 2; off > 0; off >>= 1) {
-      part.x += __shfl_xor(part.x, off, 64);
-      part.y += __shfl_xor(part.y, off, 64);
+    for (int t = 0; t < HEEV_BT_PF; ++t) {
+      const int i = ll + LPC * t;
+      if (i < m) cfmaconj<double>(part, vr[t], zc[j + 1 + i]);
     }
-    if (ll == 0) dots[0][cc] = cmul<double>(tau, part);
+    for (int i = ll + LPC * HEEV_BT_PF; i < m; i += LPC) cfmaconj<double>(part, gload(v + i), zc[j + 1 + i]);
+    part.x = half_wave_sum_dpp(part.x);
+    part.y = half_wave_sum_dpp(part.y);
+    if (ll == LPC - 1) dots[0][cc] = cmul<double>(tau, part);
     __syncthreads();
     const double2 sc = dots[0][cc];
-    for (int i = ll; i < m; i += LPC) {
-      double2& zz = zs[(j + 1 + i) * HEEV_BT_COLS + cc];
-      zz = csub<double>(zz, cmul<double>(sc, v[i]));
+#pragma unroll
+    for (int t = 0; t < HEEV_BT_PF; ++t) {
+      const int i = ll + LPC * t;
+      if (i < m) {
+        double2& zz = zc[j + 1 + i];
+        zz = csub<double>(zz, cmul<double>(sc, vr[t]));
+      }
+    }
+    for (int i = ll + LPC * HEEV_BT_PF; i < m; i += LPC) {
+      double2& zz = zc[j + 1 + i];
+      zz = csub<double>(zz, cmul<double>(sc, gload(v + i)));
     }
     __syncthreads();
+  };
+  double2 va[HEEV_BT_PF], vb[HEEV_BT_PF];
+  fetch(n - 2, va);
+  __syncthreads();
+  for (int j = n - 2; j >= 0; j -= 2) {
+    fetch(j - 1, vb);
+    apply(j, va);
+    if (j - 1 < 0) break;
+    fetch(j - 2, va);
+    apply(j - 1, vb);
   }
   for (int e = tid; e < n * ncol; e += HEEV_THREADS) {
     const int i = e / ncol, c = e - i * ncol;
-    J.v[(size_t)i * J.ldv + c0 + c] = zs[i * HEEV_BT_COLS + c];
+    J.v[(size_t)i * J.ldv + c0 + c] = zs[c * n + i];
   }
 }
 
