@@ -92,6 +92,7 @@ __device__ inline void gstore(double2* p, double2 v) {
   *(PTT_GLOBAL ptt_d2v*)p = t;
 }
 __device__ inline void gstore(double* p, double v) { *(PTT_GLOBAL double*)p = v; }
+__device__ inline double gload(const double* p) { return *(const PTT_GLOBAL double*)p; }
 
 // Block-wide sum of one double (all threads get the result).  `red` must
 // hold one double per wave.

@@ -99,6 +99,9 @@ constexpr int HEEV_SOLVE_THREADS = 1024;   // solve kernel (stages 1-4)
 __device__ inline int ldl_negcount(const double* d, const double* lld, int n, double sigma, double pivmin) {
   int cnt = 0;
   double s = -sigma;
+  // unrolled so that the reads of d and lld, which do not depend on the
+  // recurrence, are issued ahead of it
+#pragma unroll 4
   for (int i = 0; i + 1 < n; ++i) {
     double dp = d[i] + s;
     if (fabs(dp) < pivmin) dp = -pivmin;
@@ -439,10 +442,19 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
   double* ld = buf + 2048;
   double* lld = buf + 3072;
   double* mu = buf + 4096;
+  // T staged in LDS for the sequential loops of thread 0 (the slots are
+  // stage 3's, written only after this stage)
+  double* sdd = buf + 5120;
+  double* see = buf + 6144;
+  for (int i = tid; i < n; i += NT) {
+    sdd[i] = gload(dd + i);
+    see[i] = gload(ee + i);
+  }
+  __syncthreads();
   if (tid == 0) {
     double tn = 0.0;
     for (int i = 0; i < n; ++i) {
-      const double r = fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+      const double r = fabs(sdd[i]) + (i > 0 ? fabs(see[i - 1]) : 0.0) + (i + 1 < n ? fabs(see[i]) : 0.0);
       tn = fmax(tn, r);
     }
     s_tnorm = tn;
@@ -451,8 +463,9 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     int nb = 0;
     s_bs[0] = 0;
     for (int i = 0; i + 1 < n; ++i)
-      if (fabs(ee[i]) <= 2.2e-16 * tn) {
-        ee[i] = 0.0;
+      if (fabs(see[i]) <= 2.2e-16 * tn) {
+        see[i] = 0.0;
+        gstore(ee + i, 0.0);
         s_bs[++nb] = i + 1;
       }
     s_bs[++nb] = n;
@@ -462,16 +475,16 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     if (tn > 0.0) {
       for (int attempt = 0; attempt < 64 && !ok; ++attempt) {
         ok = 1;
-        double di = dd[0] + delta;
+        double di = sdd[0] + delta;
         for (int i = 0; i < n; ++i) {
           if (!(di > 1e-300 * fmax(tn, 1.0))) { ok = 0; break; }
           d[i] = di;
           if (i + 1 < n) {
-            const double li = ee[i] / di;
+            const double li = see[i] / di;
             l[i] = li;
             ld[i] = li * di;
             lld[i] = li * li * di;
-            di = (dd[i + 1] + delta) - li * ee[i];
+            di = (sdd[i + 1] + delta) - li * see[i];
           }
         }
         if (!ok) delta = fmin(delta * 8.0, 4.0 * tn);
@@ -670,6 +683,23 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     r0 = s_bs[b];
     r1 = s_bs[b + 1];
   };
+  // x / y from the hardware reciprocal and two Newton steps (a rounding-level
+  // perturbation, which the factorisations tolerate as their own rounding)
+  auto qdiv = [](double x, double y) {
+    double r = __builtin_amdgcn_rcp(y);
+    double e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    return x * r;
+  };
+  // the per-vector arrays in global memory, through global-space accesses;
+  // the loops that read back what they stored load TWIST_AHEAD entries ahead
+  constexpr int TWIST_AHEAD = 4;
+  auto wld = [&](int arr, int i, int k) { return gload(&J.work[((size_t)arr * nc + i) * nc + k]); };
+  auto wst = [&](int arr, int i, int k, double v) { gstore(&J.work[((size_t)arr * nc + i) * nc + k], v); };
+  auto zst = [&](int i, int k, double v) { gstore(&J.z[(size_t)i * nc + k], v); };
+  auto zld = [&](int i, int k) { return gload(&J.z[(size_t)i * nc + k]); };
   for (int k = tid; k < nres; k += NT) {
     const double m_k = mu[n - 1 - k];
     int r0, r1;
@@ -677,45 +707,73 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     // top-down (stationary)
     double s = -m_k;
     for (int i = r0; i + 1 < r1; ++i) {
-      W(1, i, k) = s;
+      wst(1, i, k, s);
       double dp = d[i] + s;
       if (fabs(dp) < pivmin) dp = dp < 0.0 ? -pivmin : pivmin;
-      W(0, i, k) = ld[i] / dp;
-      s = lld[i] * (s / dp) - m_k;
+      const double idp = qdiv(1.0, dp);
+      wst(0, i, k, ld[i] * idp);
+      s = lld[i] * (s * idp) - m_k;
     }
-    W(1, r1 - 1, k) = s;
+    wst(1, r1 - 1, k, s);
     // bottom-up (progressive) with the twist index
     double p = d[r1 - 1] - m_k;
-    double gmin = fabs(W(1, r1 - 1, k) + p + m_k);
+    double gmin = fabs(s + p + m_k);
     int r = r1 - 1;
-    for (int i = r1 - 2; i >= r0; --i) {
-      double dm = lld[i] + p;
-      if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
-      const double t = d[i] / dm;
-      W(2, i, k) = l[i] * t;
-      p = p * t - m_k;
-      const double g = fabs(W(1, i, k) + p + m_k);
-      if (g < gmin) { gmin = g; r = i; }
+    for (int i0 = r1 - 2; i0 >= r0; i0 -= TWIST_AHEAD) {
+      double sv[TWIST_AHEAD];
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) sv[u] = wld(1, max(i0 - u, r0), k);
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) {
+        const int i = i0 - u;
+        if (i >= r0) {
+          double dm = lld[i] + p;
+          if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
+          const double t = qdiv(d[i], dm);
+          wst(2, i, k, l[i] * t);
+          p = p * t - m_k;
+          const double g = fabs(sv[u] + p + m_k);
+          if (g < gmin) { gmin = g; r = i; }
+        }
+      }
     }
     // solve
     double z = 1.0, nrm = 1.0;
-    Z(r, k) = 1.0;
-    for (int i = r - 1; i >= r0; --i) {
-      z = -W(0, i, k) * z;
-      Z(i, k) = z;
-      nrm += z * z;
+    zst(r, k, 1.0);
+    for (int i0 = r - 1; i0 >= r0; i0 -= TWIST_AHEAD) {
+      double wv[TWIST_AHEAD];
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) wv[u] = wld(0, max(i0 - u, r0), k);
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) {
+        const int i = i0 - u;
+        if (i >= r0) {
+          z = -wv[u] * z;
+          zst(i, k, z);
+          nrm += z * z;
+        }
+      }
     }
     z = 1.0;
-    for (int i = r; i + 1 < r1; ++i) {
-      z = -W(2, i, k) * z;
-      Z(i + 1, k) = z;
-      nrm += z * z;
+    for (int i0 = r; i0 + 1 < r1; i0 += TWIST_AHEAD) {
+      double wv[TWIST_AHEAD];
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) wv[u] = wld(2, min(i0 + u, r1 - 2), k);
+#pragma unroll
+      for (int u = 0; u < TWIST_AHEAD; ++u) {
+        const int i = i0 + u;
+        if (i + 1 < r1) {
+          z = -wv[u] * z;
+          zst(i + 1, k, z);
+          nrm += z * z;
+        }
+      }
     }
     const double inv = (nrm > 0.0 && nrm < 1e300) ? 1.0 / sqrt(nrm) : 0.0;
     for (int i = 0; i < n; ++i) {
       const bool in = i >= r0 && i < r1;
       // overflow: fall back to the unit vector at the twist index
-      Z(i, k) = !in ? 0.0 : (inv > 0.0 ? Z(i, k) * inv : (i == r ? 1.0 : 0.0));
+      zst(i, k, !in ? 0.0 : (inv > 0.0 ? zld(i, k) * inv : (i == r ? 1.0 : 0.0)));
     }
   }
   __syncthreads();
