@@ -108,6 +108,18 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// block_sum with DPP wave sums (no LDS round trips inside a wave).  `red`
+// must hold one double per wave.
+__device__ inline double block_sum_dpp(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum_dpp(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  return wave_sum_dpp(lane < nw ? red[lane] : 0.0);
+}
+
 // ------------------------------------------------------------------ RNG
 // SplitMix64 finaliser (Steele, Lea, Flood 2014) used as a counter-based
 // generator: value = mix(seed + counter * golden_gamma).

@@ -934,57 +934,137 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
     double* dots = buf + 6144;  // <= 1024 coefficients
     double* gsp = buf + 7168;   // NT partial sums
     int* refs = reinterpret_cast<int*>(buf + 5120);  // <= 1024 reference indices
-    // z_j -= sum_t (z_refs[t] . z_j) z_refs[t], then z_j / |z_j|; passes
-    // of classical Gram-Schmidt against the nref vectors listed in refs
-    auto gram_schmidt = [&](int j, int nref, int passes) {
+    // z_j -= sum_t (z_p(t) . z_j) z_p(t), then z_j / |z_j|; passes of
+    // classical Gram-Schmidt against nref references: p(t) = ref_base + t,
+    // or refs[t] if ref_base < 0.  z_j is staged in LDS (the factors of
+    // stages 2-4 are no longer needed); the latency of the global loads, not
+    // their number, sets the cost of a call, so the rows of each dot product
+    // are split over up to 32 thread groups
+    double* zj = buf;
+    auto gram_schmidt = [&](int j, int nref, int passes, int ref_base) {
+      auto refp = [&](int t) { return ref_base >= 0 ? ref_base + t : refs[t]; };
       for (int pass = 0; pass < passes; ++pass) {
-        // dots[t] = z_p(t) . z_j: 256 references at a time, the rows split
-        // over four thread groups (partial sums in LDS, added in a fixed
-        // order); rows of Z are contiguous in the vector index
-        const int rows_per = (n + 3) >> 2;
-        for (int c0 = 0; c0 < nref; c0 += 256) {
-          const int t = c0 + (tid & 255), g = tid >> 8;
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-          if (t < nref) {
-            const int p = refs[t];
+        for (int i = tid; i < n; i += NT) zj[i] = zld(i, j);
+        __syncthreads();
+        // dots[t] = z_p(t) . z_j, NT references at a time; partial sums in
+        // LDS, added in a fixed order
+        for (int c0 = 0; c0 < nref; c0 += NT) {
+          const int cn = min(NT, nref - c0);
+          const int groups = min(max(1, NT / cn), 32);
+          const int rows_per = (n + groups - 1) / groups;
+          const int t = tid % cn, g = tid / cn;
+          if (g < groups) {
+            const int p = refp(c0 + t);
             const int i0 = g * rows_per, i1 = min(n, i0 + rows_per);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             int i = i0;
             for (; i + 3 < i1; i += 4) {
-              a0 += Z(i, p) * Z(i, j);
-              a1 += Z(i + 1, p) * Z(i + 1, j);
-              a2 += Z(i + 2, p) * Z(i + 2, j);
-              a3 += Z(i + 3, p) * Z(i + 3, j);
+              a0 += zld(i, p) * zj[i];
+              a1 += zld(i + 1, p) * zj[i + 1];
+              a2 += zld(i + 2, p) * zj[i + 2];
+              a3 += zld(i + 3, p) * zj[i + 3];
             }
-            for (; i < i1; ++i) a0 += Z(i, p) * Z(i, j);
+            for (; i < i1; ++i) a0 += zld(i, p) * zj[i];
+            gsp[tid] = (a0 + a1) + (a2 + a3);
           }
-          gsp[tid] = (a0 + a1) + (a2 + a3);
           __syncthreads();
-          if (tid < 256 && c0 + tid < nref) dots[c0 + tid] = ((gsp[tid] + gsp[256 + tid]) + gsp[512 + tid]) + gsp[768 + tid];
+          for (int tt = tid; tt < cn; tt += NT) {
+            double sum = 0.0;
+            for (int gg = 0; gg < groups; ++gg) sum += gsp[gg * cn + tt];
+            dots[c0 + tt] = sum;
+          }
           __syncthreads();
         }
-        // z_j -= sum_t dots[t] z_p(t): four lanes per row, combined by shuffles
+        // z_j -= sum_t dots[t] z_p(t): four lanes per row, combined by
+        // shuffles; the row stays in LDS for the normalisation
         double part = 0.0;
         const int q = tid & 3;
         for (int i = tid >> 2; i < n; i += NT >> 2) {
           double s0 = 0.0, s1 = 0.0;
           int t = q;
           for (; t + 4 < nref; t += 8) {
-            s0 += dots[t] * Z(i, refs[t]);
-            s1 += dots[t + 4] * Z(i, refs[t + 4]);
+            s0 += dots[t] * zld(i, refp(t));
+            s1 += dots[t + 4] * zld(i, refp(t + 4));
           }
-          for (; t < nref; t += 4) s0 += dots[t] * Z(i, refs[t]);
+          for (; t < nref; t += 4) s0 += dots[t] * zld(i, refp(t));
           double sum = s0 + s1;
           sum += __shfl_xor(sum, 1, 64);
           sum += __shfl_xor(sum, 2, 64);
-          const double zi = Z(i, j) - sum;
+          const double zi = zj[i] - sum;
           if (q == 0) {
-            Z(i, j) = zi;
+            zj[i] = zi;
             part += zi * zi;
           }
         }
-        const double nr = block_sum(part, red);
+        const double nr = block_sum_dpp(part, red);
         const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-        for (int i = tid; i < n; i += NT) Z(i, j) *= inv;
+        for (int i = tid; i < n; i += NT) zst(i, j, zj[i] * inv);
+        __syncthreads();
+      }
+    };
+    // two block passes of z_(c_lo+c) -= sum_t z_p(t) (z_p(t) . z_(c_lo+c))
+    // for the mc columns from c_lo, against the nref references p(t) = ra + t
+    // (t < na), rb + t - na (t >= na); coefficients C[t][c] in work array 7
+    auto project = [&](int ra, int na, int rb, int nref, int c_lo, int mc) {
+      if (nref <= 0 || mc <= 0) return;
+      double* C = J.work + (size_t)7 * nc * nc;
+      auto ref = [&](int t) { return t < na ? ra + t : rb + (t - na); };
+      // 4 x 4 register blocks: eight loads feed sixteen multiply-adds
+      const int tb = (nref + 3) >> 2, cb = (mc + 3) >> 2, ib = (n + 3) >> 2;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = tid; q < tb * cb; q += NT) {
+          const int t0 = (q / cb) * 4, c0 = (q % cb) * 4;
+          int pt[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pt[u] = ref(min(t0 + u, nref - 1));
+          double acc[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+          for (int i = 0; i < n; ++i) {
+            double zp[4], zm[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) zp[u] = zld(i, pt[u]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zm[v] = zld(i, c_lo + min(c0 + v, mc - 1));
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] = fma(zp[u], zm[v], acc[u][v]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (t0 + u < nref && c0 + v < mc) gstore(C + (size_t)(t0 + u) * nc + c0 + v, acc[u][v]);
+        }
+        __syncthreads();
+        for (int q = tid; q < ib * cb; q += NT) {
+          const int i0 = (q / cb) * 4, c0 = (q % cb) * 4;
+          double acc[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+          for (int t = 0; t < nref; ++t) {
+            const int p = ref(t);
+            double zr[4], cv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) zr[u] = zld(min(i0 + u, n - 1), p);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cv[v] = gload(C + (size_t)t * nc + min(c0 + v, mc - 1));
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] = fma(zr[u], cv[v], acc[u][v]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (i0 + u < n && c0 + v < mc) zst(i0 + u, c_lo + c0 + v, zld(i0 + u, c_lo + c0 + v) - acc[u][v]);
+        }
         __syncthreads();
       }
     };
@@ -994,82 +1074,14 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
         int e = k + 1;
         while (e < nres && is_noise(e)) ++e;
         // the whole cluster at once against every other vector (two block
-        // passes, coefficients C[t][c] in work array 7), then Gram-Schmidt
-        // inside the cluster only
-        const int m = e - k, r1 = k, nref = k + (nres - e);
-        double* C = J.work + (size_t)7 * nc * nc;
-        // 4 x 4 register blocks: eight loads feed sixteen multiply-adds
-        const int tb = (nref + 3) >> 2, cb = (m + 3) >> 2, ib = (n + 3) >> 2;
-        for (int pass = 0; pass < 2; ++pass) {
-          // C[t][c] = z_p(t) . z_(k+c)
-          for (int q = tid; q < tb * cb; q += NT) {
-            const int t0 = (q / cb) * 4, c0 = (q % cb) * 4;
-            int pt[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int t = min(t0 + u, nref - 1);
-              pt[u] = (t < r1) ? t : e + (t - r1);
-            }
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-            for (int i = 0; i < n; ++i) {
-              double zp[4], zm[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) zp[u] = Z(i, pt[u]);
-#pragma unroll
-              for (int v = 0; v < 4; ++v) zm[v] = Z(i, k + min(c0 + v, m - 1));
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(zp[u], zm[v], acc[u][v]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                if (t0 + u < nref && c0 + v < m) C[(size_t)(t0 + u) * nc + c0 + v] = acc[u][v];
-          }
-          __syncthreads();
-          // z_(k+c) -= sum_t z_p(t) C[t][c]
-          for (int q = tid; q < ib * cb; q += NT) {
-            const int i0 = (q / cb) * 4, c0 = (q % cb) * 4;
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-            for (int t = 0; t < nref; ++t) {
-              const int p = (t < r1) ? t : e + (t - r1);
-              double zr[4], cv[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) zr[u] = Z(min(i0 + u, n - 1), p);
-#pragma unroll
-              for (int v = 0; v < 4; ++v) cv[v] = C[(size_t)t * nc + min(c0 + v, m - 1)];
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(zr[u], cv[v], acc[u][v]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                if (i0 + u < n && c0 + v < m) Z(i0 + u, k + c0 + v) -= acc[u][v];
-          }
-          __syncthreads();
-        }
+        // passes), then Gram-Schmidt inside the cluster only
+        const int m = e - k;
+        project(0, k, e, k + (nres - e), k, m);
         // the members are random vectors already projected off every other
         // vector and well conditioned among themselves: one pass, the block
         // Gram-Schmidt of stage 6 (or the caller's Cholesky pass) removes
         // the second-order overlaps
-        for (int j = k; j < e; ++j) {
-          for (int t = tid; t < j - k; t += NT) refs[t] = k + t;
-          __syncthreads();
-          gram_schmidt(j, j - k, 1);
-        }
+        for (int j = k; j < e; ++j) gram_schmidt(j, j - k, 1, k);
         continue;
       }
       if (!is_member(k)) continue;
@@ -1087,7 +1099,7 @@ __global__ void __launch_bounds__(HEEV_SOLVE_THREADS) heev_solve_kernel(const He
         s_nref = c;
       }
       __syncthreads();
-      gram_schmidt(k, s_nref, 2);
+      gram_schmidt(k, s_nref, 2, -1);
     }
   }
   __syncthreads();
