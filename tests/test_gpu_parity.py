@@ -44,7 +44,7 @@ def _heev(n, a, rule=0, eps=0.0, cap=0):
     return w, v.view(np.complex128).reshape(n, n), nv.value
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 64, 100, 127, 128, 129, 256, 300])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 64, 100, 127, 128, 129, 256, 300, 600, 1024])
 def test_heev_random_hermitian(n):
     print(f"heev n={n}", flush=True)
     rng = np.random.default_rng(n)
