@@ -2,8 +2,9 @@
 // problem.  Used for every Gram matrix of the bond update (the truncated
 // SVDs of Appendix A.2 are computed from Gram matrices).
 //
-//  stage 1  Householder reduction A = Q T Q^H, T real symmetric tridiagonal
-//           (reflector H_j = I - tau_j v_j v_j^H, H_j^H x = beta e_1)
+//  stage 1  (its own kernel) Householder reduction A = Q T Q^H, T real
+//           symmetric tridiagonal (reflector H_j = I - tau_j v_j v_j^H,
+//           H_j^H x = beta e_1)
 //  stage 2  off-diagonal entries of T at the rounding level of |T| are set
 //           to zero, which splits T into unreduced blocks; then
 //           T + delta I = L D L^T with D > 0 (delta a few ulps of |T|, more
@@ -135,8 +136,9 @@ __device__ inline int ldl_negcount(const double* d, const double* lld, int n, do
 // v_r) that are the same for the whole row; a thread owns two columns, so
 // each such LDS read serves two elements.  While the trailing
 // block is larger than TRI_RES the pass reads and writes it in global
-// memory, coalesced along rows, TRI_DEPTH rows of loads in flight per
-// thread.  Once it fits, the block moves into registers (wave w holds rows
+// memory, coalesced along rows (lane p owns columns p and p + ceil(m/2)),
+// with the loads of the next batch of TRI_DEPTH rows issued while the
+// current batch is updated.  Once it fits, the block moves into registers (wave w holds rows
 // w + 8 k, lane l columns 2 l and 2 l + 1: 128 registers per thread, which
 // eight waves of 256 registers hold without spilling) and the remaining
 // steps touch no memory but the vectors in LDS; the row that the next step
