@@ -36,9 +36,11 @@ pt_tebd_status pt_test_heev_tridiagonal(int32_t n, const double* a, int32_t rule
  * averaged over reps runs on fresh copies of a: stage_ms[0..5] the
  * tridiagonal reduction, the shifted factorisation, the eigenvalues, the
  * selection rule, the twisted eigenvectors and the cluster pass (device
- * wall clock inside the kernel), stage_ms[6] the whole solve kernel and
- * stage_ms[7] the back-transformation plus the two orthonormalisation
- * passes (HIP events).  stage_ms holds 9 doubles ([8] is zero). */
+ * wall clock inside the kernels; the factorisation's time includes the
+ * launch gap between the reduction kernel and the stage 2-4 kernel),
+ * stage_ms[6] the two kernels together and stage_ms[7] the
+ * back-transformation plus the two orthonormalisation passes (HIP events).
+ * stage_ms holds 9 doubles ([8] is zero). */
 pt_tebd_status pt_test_heev_profile(int32_t n, const double* a, int32_t rule, double eps, int32_t reps,
                                     double* stage_ms);
 
